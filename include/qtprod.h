@@ -1,0 +1,159 @@
+/*
+ * qtprod.h -- C-ABI of libqtprod.so: the fast T-product of third-order
+ * quaternion tensors on AMD Instinct MI355X (gfx950).
+ *
+ * Method (Zheng & Ni, "Block diagonalization of block circulant quaternion
+ * matrices and the fast calculation for T-product of quaternion tensors"):
+ * the T-product C = A * B := fold(bcirc(A) . unfold(B)) (Section 2.4,
+ * Definition of the T-product) of A (m x n x p) and B (n x s x p) is computed
+ * in three device steps, all hand-written HIP kernels:
+ *   1. a tube FFT along the third mode of the Cayley-Dickson parts A1, A2,
+ *      B1, B2 (Theorem 4.4: the block diagonalisation of bcirc is a DFT of the
+ *      tubes);
+ *   2. facewise complex products in the Fourier domain, where frequency f is
+ *      coupled with frequency -f mod p because j c = conj(c) j
+ *      (Theorem 5.1, Remark 5.1):
+ *        C1^[f] = A1^[f] B1^[f] - A2^[f] conj(B2^[-f])
+ *        C2^[f] = A1^[f] B2^[f] + A2^[f] conj(B1^[-f])
+ *   3. the inverse tube FFT (Remark 4.3 (iv), Remark 5.1).
+ * Steps 1-3 are Algorithm 5.1 written with a plain forward DFT
+ * (omega = exp(-2 pi i / p), unnormalised) and 1/p in the inverse; the
+ * paper's conj-FFT convention gives the same C.
+ *
+ * ---------------------------------------------------------------- layout --
+ * A quaternion tensor X of size rows x cols x p is ONE device buffer of
+ * 4 * p * rows * cols reals, planar, C order [4][p][rows][cols]:
+ *   plane 0 = a, plane 1 = b, plane 2 = c, plane 3 = d of a + b i + c j + d k,
+ * which in Cayley-Dickson form X = X1 + X2 j (Section 2.2) is
+ *   plane 0 = Re X1, plane 1 = Im X1, plane 2 = Re X2, plane 3 = Im X2.
+ * Face k (0-based; face k + 1 of the paper) of plane c starts at element
+ * (c * p + k) * rows * cols.  Reals are float (QT_FP32, QT_SPLIT_BF16) or
+ * double (QT_FP64).
+ *
+ * ------------------------------------------------------------ ownership --
+ * The caller owns every input, output and workspace buffer; the library never
+ * frees them.  The library owns only its plan cache: one small twiddle table
+ * per (device, p), generated in FP64 on the GPU on first use (that first call
+ * allocates it with hipMalloc and synchronises the stream once), kept until
+ * the library is unloaded.  Call qt_prepare(p) before capturing a HIP graph.
+ *
+ * ------------------------------------------------------------ semantics --
+ * Every compute call is asynchronous on `stream` (NULL = the null stream)
+ * and never synchronises with the host except the one-time plan creation.
+ * Argument errors are detected on the host before any launch and returned
+ * synchronously; a HIP launch error is returned as QT_ERR_HIP.  Faults inside
+ * kernels surface at the caller's next synchronisation.
+ *
+ * Preconditions checked (QT_ERR_INVALID_ARG otherwise): m, n, s, p >= 1;
+ * every pointer non-NULL and 16-byte aligned; outputs do not overlap inputs;
+ * ws_bytes >= the matching *_workspace_size(); 4 * p * rows * cols < 2^40.
+ */
+#ifndef QTPROD_H
+#define QTPROD_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QT_OK = 0,
+    QT_ERR_INVALID_ARG = -1,  /* bad size, pointer, alignment, aliasing, workspace */
+    QT_ERR_UNSUPPORTED = -2,  /* valid request this build cannot serve (e.g. p too large) */
+    QT_ERR_ALLOC = -3,        /* plan-cache allocation failed */
+    QT_ERR_HIP = -4           /* a HIP runtime call or kernel launch failed */
+} qt_status;
+
+typedef enum {
+    QT_FP32 = 0,        /* FP32 FFTs; facewise products on FP32 MFMA, FP32 accumulate */
+    QT_SPLIT_BF16 = 1,  /* FP32 FFTs; facewise products as bf16 hi+lo split:
+                           x = hi + lo, product ~ hi*hi + hi*lo + lo*hi on bf16 MFMA,
+                           FP32 accumulate */
+    QT_SPLIT_FP16 = 2,  /* as QT_SPLIT_BF16 with fp16 hi+lo and a power-of-two
+                           scale per operand plane and frequency */
+    QT_FP64 = 3         /* every step in double (small problems, validation) */
+} qt_precision;
+
+/* Largest p served.  Every p in [1, QT_MAX_P] is supported. */
+#define QT_MAX_P 4096
+
+/* Library ABI version (major * 100 + minor). */
+int qt_version(void);
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* qt_status_string(int status);
+
+/* Create the plan (twiddle table, and Bluestein chirp spectrum when p needs
+ * one) for p on the current device, on `stream`, and wait for it.  Optional:
+ * compute calls do this lazily.  Returns QT_OK, QT_ERR_INVALID_ARG,
+ * QT_ERR_UNSUPPORTED, QT_ERR_ALLOC or QT_ERR_HIP. */
+int qt_prepare(int p, hipStream_t stream);
+
+/* Tube FFT of one quaternion tensor X (rows x cols x p) -- the block
+ * diagonalisation of bcirc(X) of Theorem 4.4, in the plain-DFT convention:
+ *   inverse = 0:  Xh[c][f] = sum_k X[c][k] w^(f k), w = exp(-2 pi i / p), applied
+ *                 to the complex parts X1 = (plane 0, plane 1) and
+ *                 X2 = (plane 2, plane 3) separately;
+ *   inverse = 1:  the inverse transform, with the factor 1/p.
+ * Output Xh has the same dense layout [4][p][rows][cols], planes
+ * (Re X1^, Im X1^, Re X2^, Im X2^).  (The paper's transform of Theorem 4.4 is
+ * fft(conj X) = conj(X1^[-f]) - X2^[f] j in these terms.)  X and Xh must not
+ * overlap.  precision: QT_FP32 (float) or QT_FP64 (double). */
+int qt_tube_fft(int rows, int cols, int p, const void* X, void* Xh, int inverse,
+                int precision, hipStream_t stream);
+
+/* Workspace bytes needed by qt_tprod for these sizes and precision
+ * (0 if an argument is invalid).  Holds the Fourier-domain tensors
+ * A^, B^ and C^ (row strides rounded up to a multiple of 4 reals). */
+size_t qt_workspace_size(int m, int n, int s, int p, int precision);
+
+/* C = A * B.  A: m x n x p, B: n x s x p, C: m x s x p (layout above; all
+ * device pointers).  ws: device workspace of ws_bytes >= qt_workspace_size().
+ * C is fully overwritten.  Definition: Section 2.4; algorithm: Algorithm 5.1
+ * with Theorem 5.1. */
+int qt_tprod(int m, int n, int s, int p,
+             const void* A, const void* B, void* C,
+             int precision, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* One problem of a batch: sizes and device pointers, same layout as above. */
+typedef struct {
+    int m, n, s, p;
+    const void* A;
+    const void* B;
+    void* C;
+} qt_problem;
+
+/* Workspace bytes for qt_tprod_batched over `count` problems (host array). */
+size_t qt_batched_workspace_size(int count, const qt_problem* probs, int precision);
+
+/* C_i = A_i * B_i for count independent problems of any sizes and p, in one
+ * persistent kernel launch (plus one small descriptor upload into ws).
+ * probs is a HOST array read before the call returns.  Each problem obeys the
+ * single-call preconditions.  Results equal those of qt_tprod on each problem
+ * to within rounding (same arithmetic; tile order may differ). */
+int qt_tprod_batched(int count, const qt_problem* probs, int precision,
+                     void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Workspace bytes needed by qt_tprod_backward. */
+size_t qt_backward_workspace_size(int m, int n, int s, int p, int precision);
+
+/* Adjoints of C = A * B for an output gradient G (m x s x p):
+ *   dA = G * B^H   (m x n x p),   dB = A^H * G   (n x s x p),
+ * where X^H is the tensor conjugate transpose (face 0 -> (X_0)^*, face k ->
+ * (X_{p-k})^*; bcirc(X^H) = bcirc(X)^*).  For L = 1/2 ||A * B - T||_F^2 and
+ * G = A * B - T these are dL/dA and dL/dB of the real components.  Either of
+ * dA, dB may be NULL to skip it.  Computed in the Fourier domain with the
+ * same frequency coupling as the forward product (bcirc(A * B) =
+ * bcirc(A) bcirc(B), proof of Theorem 5.1). */
+int qt_tprod_backward(int m, int n, int s, int p,
+                      const void* A, const void* B, const void* G,
+                      void* dA, void* dB,
+                      int precision, void* ws, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QTPROD_H */

@@ -1,0 +1,222 @@
+// C-ABI entry points of libqtprod (declared in include/qtprod.h).
+//
+// Host side only: argument validation, the per-(device, p) plan cache
+// (twiddle tables), workspace carving and kernel launches.  Every step of the
+// T-product itself runs in the HIP kernels of fft.hip and facewise.hip.
+#include <mutex>
+#include <unordered_map>
+
+#include "qt_internal.h"
+#include "../../include/qtprod.h"
+
+namespace {
+
+using qt::FftJob;
+using qt::FacewiseArgs;
+using qt::Twiddles;
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+bool valid_precision(int prec) {
+    return prec == QT_FP32 || prec == QT_SPLIT_BF16 || prec == QT_SPLIT_FP16 || prec == QT_FP64;
+}
+
+size_t real_bytes(int prec) { return prec == QT_FP64 ? 8 : 4; }
+
+bool dims_ok(long rows, long cols, long p) {
+    if (rows < 1 || cols < 1 || p < 1) return false;
+    // element counts must stay far from 64-bit overflow and within 2^40
+    const double elems = 4.0 * (double)p * (double)rows * (double)qt::fourier_ld(cols);
+    return elems < (double)(1LL << 40);
+}
+
+bool aligned16(const void* ptr) { return ((uintptr_t)ptr & 15u) == 0; }
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+size_t tensor_bytes(long rows, long cols, long p, int prec) {
+    return 4 * (size_t)p * (size_t)rows * (size_t)cols * real_bytes(prec);
+}
+
+size_t fourier_bytes(long rows, long cols, long p, int prec) {
+    return align_up(4 * (size_t)p * (size_t)rows * (size_t)qt::fourier_ld(cols) * real_bytes(prec));
+}
+
+bool p_supported(int p, int prec) {
+    if (p < 1 || p > QT_MAX_P) return false;
+    return prec == QT_FP64 ? qt::tube_fft_supported<double>(p) : qt::tube_fft_supported<float>(p);
+}
+
+// ------------------------------------------------------------- plan cache
+struct PlanKey {
+    int device, p;
+    bool operator==(const PlanKey& o) const { return device == o.device && p == o.p; }
+};
+struct PlanKeyHash {
+    size_t operator()(const PlanKey& k) const { return ((size_t)k.device << 32) ^ (size_t)k.p; }
+};
+
+std::mutex g_plan_mutex;
+std::unordered_map<PlanKey, Twiddles, PlanKeyHash> g_plans;
+
+int get_plan(int p, hipStream_t stream, Twiddles* out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return QT_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_plan_mutex);
+    auto it = g_plans.find(PlanKey{dev, p});
+    if (it != g_plans.end()) {
+        *out = it->second;
+        return QT_OK;
+    }
+    Twiddles tw{nullptr, nullptr};
+    if (hipMalloc((void**)&tw.f32, sizeof(float2) * (size_t)p) != hipSuccess) return QT_ERR_ALLOC;
+    if (hipMalloc((void**)&tw.f64, sizeof(double2) * (size_t)p) != hipSuccess) {
+        (void)hipFree(tw.f32);
+        return QT_ERR_ALLOC;
+    }
+    if (qt::launch_twiddles(p, tw, stream) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) {
+        (void)hipFree(tw.f32);
+        (void)hipFree(tw.f64);
+        return QT_ERR_HIP;
+    }
+    g_plans.emplace(PlanKey{dev, p}, tw);
+    *out = tw;
+    return QT_OK;
+}
+
+// ------------------------------------------------------------- forward path
+template <typename T>
+int run_tprod(int m, int n, int s, int p, const T* A, const T* B, T* C, int prec, char* ws,
+              hipStream_t stream) {
+    Twiddles tw;
+    int st = get_plan(p, stream, &tw);
+    if (st != QT_OK) return st;
+    const int lda = (int)qt::fourier_ld(n), ldb = (int)qt::fourier_ld(s), ldc = ldb;
+    T* Ah = reinterpret_cast<T*>(ws);
+    T* Bh = reinterpret_cast<T*>(ws + fourier_bytes(m, n, p, prec));
+    T* Ch = reinterpret_cast<T*>(ws + fourier_bytes(m, n, p, prec) + fourier_bytes(n, s, p, prec));
+
+    // step 1: tube FFT of A and B (one launch)
+    FftJob<T> fwd[2] = {{A, Ah, m, n, n, lda}, {B, Bh, n, s, s, ldb}};
+    if (qt::launch_tube_fft<T>(p, false, fwd, 2, tw, stream) != hipSuccess) return QT_ERR_HIP;
+
+    // step 2: coupled facewise products
+    FacewiseArgs<T> fa{Ah, Bh, Ch, m, n, s, p, lda, ldb, ldc};
+    hipError_t e;
+    if constexpr (sizeof(T) == 8) e = qt::launch_facewise_f64(fa, stream);
+    else e = qt::launch_facewise_f32(fa, prec, stream);
+    if (e == hipErrorNotSupported) return QT_ERR_UNSUPPORTED;
+    if (e != hipSuccess) return QT_ERR_HIP;
+
+    // step 3: inverse tube FFT of C^ into C
+    FftJob<T> inv[1] = {{Ch, C, m, s, ldc, s}};
+    if (qt::launch_tube_fft<T>(p, true, inv, 1, tw, stream) != hipSuccess) return QT_ERR_HIP;
+    return QT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qt_version(void) { return 100; }
+
+const char* qt_status_string(int status) {
+    switch (status) {
+        case QT_OK: return "QT_OK";
+        case QT_ERR_INVALID_ARG: return "QT_ERR_INVALID_ARG: invalid size, pointer, alignment, aliasing or workspace";
+        case QT_ERR_UNSUPPORTED: return "QT_ERR_UNSUPPORTED: request not supported by this build";
+        case QT_ERR_ALLOC: return "QT_ERR_ALLOC: plan allocation failed";
+        case QT_ERR_HIP: return "QT_ERR_HIP: HIP runtime or launch error";
+        default: return "unknown qt_status";
+    }
+}
+
+int qt_prepare(int p, hipStream_t stream) {
+    if (p < 1) return QT_ERR_INVALID_ARG;
+    if (p > QT_MAX_P) return QT_ERR_UNSUPPORTED;
+    Twiddles tw;
+    return get_plan(p, stream, &tw);
+}
+
+int qt_tube_fft(int rows, int cols, int p, const void* X, void* Xh, int inverse, int precision,
+                hipStream_t stream) {
+    if (precision != QT_FP32 && precision != QT_FP64) return QT_ERR_INVALID_ARG;
+    if (!dims_ok(rows, cols, p) || !X || !Xh || !aligned16(X) || !aligned16(Xh))
+        return QT_ERR_INVALID_ARG;
+    if (inverse != 0 && inverse != 1) return QT_ERR_INVALID_ARG;
+    const size_t bytes = tensor_bytes(rows, cols, p, precision);
+    if (overlaps(X, bytes, Xh, bytes)) return QT_ERR_INVALID_ARG;
+    if (!p_supported(p, precision)) return QT_ERR_UNSUPPORTED;
+    Twiddles tw;
+    int st = get_plan(p, stream, &tw);
+    if (st != QT_OK) return st;
+    hipError_t e;
+    if (precision == QT_FP64) {
+        FftJob<double> j{(const double*)X, (double*)Xh, rows, cols, cols, cols};
+        e = qt::launch_tube_fft<double>(p, inverse != 0, &j, 1, tw, stream);
+    } else {
+        FftJob<float> j{(const float*)X, (float*)Xh, rows, cols, cols, cols};
+        e = qt::launch_tube_fft<float>(p, inverse != 0, &j, 1, tw, stream);
+    }
+    return e == hipSuccess ? QT_OK : QT_ERR_HIP;
+}
+
+size_t qt_workspace_size(int m, int n, int s, int p, int precision) {
+    if (!valid_precision(precision) || !dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p))
+        return 0;
+    return fourier_bytes(m, n, p, precision) + fourier_bytes(n, s, p, precision) +
+           fourier_bytes(m, s, p, precision);
+}
+
+int qt_tprod(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision,
+             void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!valid_precision(precision)) return QT_ERR_INVALID_ARG;
+    if (!dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p)) return QT_ERR_INVALID_ARG;
+    if (!A || !B || !C || !ws) return QT_ERR_INVALID_ARG;
+    if (!aligned16(A) || !aligned16(B) || !aligned16(C) || !aligned16(ws)) return QT_ERR_INVALID_ARG;
+    const size_t need = qt_workspace_size(m, n, s, p, precision);
+    if (ws_bytes < need) return QT_ERR_INVALID_ARG;
+    const size_t cb = tensor_bytes(m, s, p, precision);
+    if (overlaps(C, cb, A, tensor_bytes(m, n, p, precision)) ||
+        overlaps(C, cb, B, tensor_bytes(n, s, p, precision)) ||
+        overlaps(ws, need, A, tensor_bytes(m, n, p, precision)) ||
+        overlaps(ws, need, B, tensor_bytes(n, s, p, precision)) || overlaps(ws, need, C, cb))
+        return QT_ERR_INVALID_ARG;
+    if (!p_supported(p, precision)) return QT_ERR_UNSUPPORTED;
+    if (precision == QT_FP64)
+        return run_tprod<double>(m, n, s, p, (const double*)A, (const double*)B, (double*)C, precision,
+                                 (char*)ws, stream);
+    return run_tprod<float>(m, n, s, p, (const float*)A, (const float*)B, (float*)C, precision,
+                            (char*)ws, stream);
+}
+
+size_t qt_batched_workspace_size(int count, const qt_problem* probs, int precision) {
+    (void)count; (void)probs; (void)precision;
+    return 0;
+}
+
+int qt_tprod_batched(int count, const qt_problem* probs, int precision, void* ws, size_t ws_bytes,
+                     hipStream_t stream) {
+    (void)count; (void)probs; (void)precision; (void)ws; (void)ws_bytes; (void)stream;
+    return QT_ERR_UNSUPPORTED;
+}
+
+size_t qt_backward_workspace_size(int m, int n, int s, int p, int precision) {
+    (void)m; (void)n; (void)s; (void)p; (void)precision;
+    return 0;
+}
+
+int qt_tprod_backward(int m, int n, int s, int p, const void* A, const void* B, const void* G,
+                      void* dA, void* dB, int precision, void* ws, size_t ws_bytes,
+                      hipStream_t stream) {
+    (void)m; (void)n; (void)s; (void)p; (void)A; (void)B; (void)G; (void)dA; (void)dB;
+    (void)precision; (void)ws; (void)ws_bytes; (void)stream;
+    return QT_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,219 @@
+// Tube FFTs along the third mode of a quaternion tensor (gfx950).
+//
+// Theorem 4.4 turns the block diagonalisation of bcirc(Q) into a length-p DFT
+// of every tube Q(i, j, :); Remark 4.3 (iv) gives the inverse.  Both
+// Cayley-Dickson parts Q1 = a + b i and Q2 = c + d i are transformed with the
+// plain DFT  X^[f] = sum_k X[k] w^(f k),  w = exp(-2 pi i / p), and the
+// inverse carries 1/p.  (The paper transforms conj(Q); with the coupling
+// written for the plain transform the product C is the same.)
+//
+// Design: one thread owns one complex tube (p values of one CD part at one
+// (i, j) position) and keeps it in registers.  Consecutive threads own
+// consecutive (i, j), so for every face each wave reads and writes 64
+// consecutive reals per plane: fully coalesced and each element read once
+// and written once (32 bytes per quaternion per direction in FP32, the HBM
+// minimum).  The transform is a mixed-radix decimation-in-time FFT whose
+// length P is a template parameter, so every index is a compile-time
+// constant and the data never leaves VGPRs.  Twiddles come from a table
+// generated in FP64 on the device (uniform addresses -> scalar loads).
+#pragma once
+#include "qt_internal.h"
+
+namespace qt {
+namespace detail {
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+template <typename V>
+__device__ __forceinline__ V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
+template <typename V>
+__device__ __forceinline__ V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
+template <typename V>
+__device__ __forceinline__ V cmul(V a, V b) {
+    return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename V>
+__device__ __forceinline__ V mul_mi(V a) { return INV ? V{-a.y, a.x} : V{a.y, -a.x}; }
+
+// w_N^e for a length-N sub-transform of a length-P table, conjugated for INV.
+template <int P, int N, bool INV, typename V>
+__device__ __forceinline__ V twiddle(int e, const V* __restrict__ tw) {
+    V w = tw[(e % N) * (P / N)];
+    if (INV) w.y = -w.y;
+    return w;
+}
+
+constexpr int pick_radix(int n) {
+    return (n % 4 == 0) ? 4 : (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : (n % 5 == 0) ? 5
+         : (n % 7 == 0) ? 7 : n;
+}
+
+// In-register DFT of length R (the butterfly of one radix stage).
+template <int P, int R, bool INV, typename V>
+__device__ __forceinline__ void small_dft(V (&t)[R], const V* __restrict__ tw) {
+    if constexpr (R == 1) {
+        return;
+    } else if constexpr (R == 2) {
+        V a = t[0], b = t[1];
+        t[0] = cadd(a, b);
+        t[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        V a = t[0], b = t[1], c = t[2], d = t[3];
+        V s0 = cadd(a, c), d0 = csub(a, c);
+        V s1 = cadd(b, d), d1 = mul_mi<INV>(csub(b, d));
+        t[0] = cadd(s0, s1);
+        t[2] = csub(s0, s1);
+        t[1] = cadd(d0, d1);
+        t[3] = csub(d0, d1);
+    } else {
+        // odd prime radix: X[u] = sum_v t[v] w_R^(u v), pairing v and R - v
+        // (w^(u(R-v)) = conj(w^(uv))) to halve the multiplications.
+        V x[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) x[u] = t[u];
+        V sum = x[0];
+#pragma unroll
+        for (int v = 1; v < R; ++v) sum = cadd(sum, x[v]);
+        t[0] = sum;
+#pragma unroll
+        for (int u = 1; u < R; ++u) {
+            V acc = x[0];
+#pragma unroll
+            for (int v = 1; v <= R / 2; ++v) {
+                const V w = twiddle<P, R, INV>(u * v, tw);
+                const V sp = cadd(x[v], x[R - v]);
+                const V sm = csub(x[v], x[R - v]);
+                // x[v] w + x[R-v] conj(w) = (sp wr) + i (sm wi) componentwise
+                acc.x += sp.x * w.x - sm.y * w.y;
+                acc.y += sp.y * w.x + sm.x * w.y;
+            }
+            t[u] = acc;
+        }
+    }
+}
+
+// Decimation in time: N = R M.  Sub-transforms of the R decimated sequences
+// x[j R + r], then X[q + M u] = sum_r w_R^(r u) (w_N^(r q) Y_r[q]).
+template <int P, int N, bool INV, typename V>
+struct Dft {
+    static __device__ __forceinline__ void run(V (&x)[N], const V* __restrict__ tw) {
+        constexpr int R = pick_radix(N);
+        constexpr int M = N / R;
+        if constexpr (M == 1) {
+            small_dft<P, R, INV>(x, tw);
+        } else {
+            V sub[R][M];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int j = 0; j < M; ++j) sub[r][j] = x[j * R + r];
+#pragma unroll
+            for (int r = 0; r < R; ++r) Dft<P, M, INV, V>::run(sub[r], tw);
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                V t[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    t[r] = (r * q == 0) ? sub[r][q] : cmul(sub[r][q], twiddle<P, N, INV>(r * q, tw));
+                small_dft<P, R, INV>(t, tw);
+#pragma unroll
+                for (int u = 0; u < R; ++u) x[q + M * u] = t[u];
+            }
+        }
+    }
+};
+
+template <typename T>
+struct FftJobs2 {
+    FftJob<T> j[2];
+};
+
+// grid: x covers rows*cols of the largest job, y = 2 * njobs (job, CD part).
+template <int P, bool INV, typename T>
+__global__ void __launch_bounds__(256)
+tube_fft_kernel(FftJobs2<T> jobs, const typename Vec2<T>::type* __restrict__ tw) {
+    using V = typename Vec2<T>::type;
+    const int job = blockIdx.y >> 1;
+    const int part = blockIdx.y & 1;                 // 0: X1 (planes 0,1), 1: X2 (planes 2,3)
+    const FftJob<T> jb = jobs.j[job];
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long count = (long)jb.rows * jb.cols;
+    if (e >= count) return;
+    const int i = (int)(e / jb.cols);
+    const int c = (int)(e - (long)i * jb.cols);
+    const size_t sface = (size_t)jb.rows * jb.src_ld;
+    const size_t dface = (size_t)jb.rows * jb.dst_ld;
+    const T* __restrict__ sre = jb.src + (size_t)(2 * part) * P * sface + (size_t)i * jb.src_ld + c;
+    const T* __restrict__ sim = sre + (size_t)P * sface;
+    T* __restrict__ dre = jb.dst + (size_t)(2 * part) * P * dface + (size_t)i * jb.dst_ld + c;
+    T* __restrict__ dim = dre + (size_t)P * dface;
+
+    V x[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) x[k] = V{sre[k * sface], sim[k * sface]};
+    Dft<P, P, INV, V>::run(x, tw);
+    const T scale = INV ? T(1) / T(P) : T(1);
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        dre[k * dface] = x[k].x * scale;
+        dim[k * dface] = x[k].y * scale;
+    }
+}
+
+template <int P, bool INV, typename T>
+hipError_t launch_p(const FftJob<T>* jobs, int njobs, const Twiddles& tw, hipStream_t stream) {
+    FftJobs2<T> pk{};
+    long maxc = 0;
+    for (int q = 0; q < njobs; ++q) {
+        pk.j[q] = jobs[q];
+        maxc = (long)jobs[q].rows * jobs[q].cols > maxc ? (long)jobs[q].rows * jobs[q].cols : maxc;
+    }
+    const dim3 block(256);
+    const dim3 grid((unsigned)((maxc + 255) / 256), 2 * njobs);
+    const typename Vec2<T>::type* t;
+    if constexpr (sizeof(T) == 4) t = tw.f32; else t = tw.f64;
+    hipLaunchKernelGGL((tube_fft_kernel<P, INV, T>), grid, block, 0, stream, pk, t);
+    return hipGetLastError();
+}
+
+}  // namespace detail
+}  // namespace qt
+
+// Register-resident lengths, split into groups that compile in separate
+// translation units (fft_inst_*.hip): 7-smooth p, FP32 up to 128 and FP64 up
+// to 64 (bounded by the VGPR budget of one tube per thread).
+#define QT_FFT_SIZES_G0(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(12) X(14) X(15) \
+    X(16) X(18) X(20) X(21) X(24) X(25) X(27) X(28) X(30) X(32)
+#define QT_FFT_SIZES_G1(X) X(35) X(36) X(40) X(42) X(45) X(48) X(49) X(50)
+#define QT_FFT_SIZES_G2(X) X(54) X(56) X(60) X(63) X(64)
+#define QT_FFT_SIZES_G3(X) X(70) X(72) X(75) X(80) X(81) X(84) X(90)
+#define QT_FFT_SIZES_G4(X) X(96) X(98) X(100) X(105)
+#define QT_FFT_SIZES_G5(X) X(108) X(112) X(120) X(125) X(126) X(128)
+
+#define QT_FFT_SIZES_F64(X) QT_FFT_SIZES_G0(X) QT_FFT_SIZES_G1(X) QT_FFT_SIZES_G2(X)
+#define QT_FFT_SIZES_F32(X) QT_FFT_SIZES_F64(X) QT_FFT_SIZES_G3(X) QT_FFT_SIZES_G4(X) \
+    QT_FFT_SIZES_G5(X)
+
+#define QT_FFT_EXTERN_F32(P)                                                              \
+    extern template hipError_t qt::detail::launch_p<P, false, float>(                    \
+        const qt::FftJob<float>*, int, const qt::Twiddles&, hipStream_t);               \
+    extern template hipError_t qt::detail::launch_p<P, true, float>(                     \
+        const qt::FftJob<float>*, int, const qt::Twiddles&, hipStream_t);
+#define QT_FFT_EXTERN_F64(P)                                                              \
+    extern template hipError_t qt::detail::launch_p<P, false, double>(                   \
+        const qt::FftJob<double>*, int, const qt::Twiddles&, hipStream_t);              \
+    extern template hipError_t qt::detail::launch_p<P, true, double>(                    \
+        const qt::FftJob<double>*, int, const qt::Twiddles&, hipStream_t);
+#define QT_FFT_INST_F32(P)                                                                \
+    template hipError_t qt::detail::launch_p<P, false, float>(                           \
+        const qt::FftJob<float>*, int, const qt::Twiddles&, hipStream_t);               \
+    template hipError_t qt::detail::launch_p<P, true, float>(                            \
+        const qt::FftJob<float>*, int, const qt::Twiddles&, hipStream_t);
+#define QT_FFT_INST_F64(P)                                                                \
+    template hipError_t qt::detail::launch_p<P, false, double>(                          \
+        const qt::FftJob<double>*, int, const qt::Twiddles&, hipStream_t);              \
+    template hipError_t qt::detail::launch_p<P, true, double>(                           \
+        const qt::FftJob<double>*, int, const qt::Twiddles&, hipStream_t);

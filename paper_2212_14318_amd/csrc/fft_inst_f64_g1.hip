@@ -1,0 +1,3 @@
+// Register-resident FP64 tube-FFT kernels, length group 1.
+#include "fft_impl.h"
+QT_FFT_SIZES_G1(QT_FFT_INST_F64)

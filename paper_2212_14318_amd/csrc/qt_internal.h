@@ -1,0 +1,66 @@
+// Internal declarations shared by the HIP translation units of libqtprod.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace qt {
+
+// Row stride (in reals) of a Fourier-domain matrix: columns rounded up to a
+// multiple of 4 so that every row starts 16-byte aligned for vector loads.
+inline long fourier_ld(long cols) { return (cols + 3) & ~3L; }
+
+// Plane stride of a tensor stored as [4][p][rows][ld].
+inline size_t plane_elems(long p, long rows, long ld) { return (size_t)p * (size_t)rows * (size_t)ld; }
+
+// One tube-FFT job: a quaternion tensor of rows x cols x p, read from `src`
+// with row stride src_ld and written to `dst` with row stride dst_ld.  Both
+// buffers are [4][p][rows][ld].  Planes (0,1) form the complex part X1,
+// planes (2,3) the part X2 of the Cayley-Dickson form.
+template <typename T>
+struct FftJob {
+    const T* src;
+    T* dst;
+    int rows, cols, src_ld, dst_ld;
+};
+
+// Twiddle tables of one p: tw[k] = exp(-2 pi i k / p), k in [0, p), made in
+// FP64 on the device and stored in both precisions.
+struct Twiddles {
+    float2* f32;
+    double2* f64;
+};
+
+// Forward (inverse = false) or inverse (inverse = true, with the 1/p scale)
+// tube FFT of up to two jobs in one launch.  Returns hipSuccess or the launch
+// error; hipErrorNotSupported if p has no kernel in this build.
+template <typename T>
+hipError_t launch_tube_fft(int p, bool inverse, const FftJob<T>* jobs, int njobs,
+                           const Twiddles& tw, hipStream_t stream);
+
+// True if launch_tube_fft has a kernel for this p and element type.
+template <typename T>
+bool tube_fft_supported(int p);
+
+// Generate the twiddle table of p on `stream` (FP64 sincos on the device).
+hipError_t launch_twiddles(int p, Twiddles tw, hipStream_t stream);
+
+// Operands of the coupled facewise products for one problem, all in the
+// Fourier domain, [4][p][rows][ld] layout:
+//   A^: m x n (row stride lda), B^: n x s (ldb), C^: m x s (ldc).
+template <typename T>
+struct FacewiseArgs {
+    const T* Ah;
+    const T* Bh;
+    T* Ch;
+    int m, n, s, p;
+    int lda, ldb, ldc;
+};
+
+// C^[f] = A^[f] B^[f] coupled with -f (see qtprod.h) for every f.
+// precision: 0 = FP32 MFMA, 1 = split bf16, 2 = split fp16 (float only).
+hipError_t launch_facewise_f32(const FacewiseArgs<float>& a, int precision, hipStream_t stream);
+hipError_t launch_facewise_f64(const FacewiseArgs<double>& a, hipStream_t stream);
+
+}  // namespace qt

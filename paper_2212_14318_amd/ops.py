@@ -1,0 +1,154 @@
+"""Torch-facing wrappers over the C-ABI: device memory, streams, autograd.
+
+Torch supplies device buffers and the current HIP stream; every step of the
+T-product runs in libqtprod's kernels.  Tensors are quaternion tensors in the
+planar layout of the C-ABI: shape (4, p, rows, cols), contiguous, float32
+(float64 for precision "fp64"), on a ROCm device.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _native as nat
+
+
+def _prec(precision) -> int:
+    if isinstance(precision, int):
+        return precision
+    try:
+        return nat.PRECISIONS[precision]
+    except KeyError:
+        raise ValueError(f"unknown precision {precision!r}; use one of {list(nat.PRECISIONS)}")
+
+
+def _dtype(prec: int):
+    return torch.float64 if prec == nat.QT_FP64 else torch.float32
+
+
+def _check_tensor(x: torch.Tensor, name: str, prec: int):
+    if not isinstance(x, torch.Tensor) or x.dim() != 4 or x.shape[0] != 4:
+        raise ValueError(f"{name} must be a tensor of shape (4, p, rows, cols)")
+    if x.device.type != "cuda":
+        raise ValueError(f"{name} must live on a ROCm device")
+    if x.dtype != _dtype(prec):
+        raise ValueError(f"{name} must be {_dtype(prec)} for this precision, got {x.dtype}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _stream(dev) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    """A device byte buffer of at least nbytes (256-byte aligned by torch)."""
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def tube_fft(X: torch.Tensor, inverse: bool = False, precision="fp32") -> torch.Tensor:
+    """Tube FFT of a quaternion tensor (block diagonalisation of bcirc(X))."""
+    prec = _prec(precision)
+    _check_tensor(X, "X", prec)
+    _, p, rows, cols = X.shape
+    out = torch.empty_like(X)
+    st = nat.qt_tube_fft(rows, cols, p, X.data_ptr(), out.data_ptr(), int(bool(inverse)), prec,
+                         _stream(X.device))
+    nat.check(st, "qt_tube_fft")
+    return out
+
+
+def tprod(A: torch.Tensor, B: torch.Tensor, precision="fp32", out: torch.Tensor | None = None,
+          ws: torch.Tensor | None = None) -> torch.Tensor:
+    """C = A * B (T-product of quaternion tensors) on the GPU."""
+    prec = _prec(precision)
+    _check_tensor(A, "A", prec)
+    _check_tensor(B, "B", prec)
+    _, p, m, n = A.shape
+    if B.shape[1] != p or B.shape[2] != n:
+        raise ValueError("B must be n x s x p with A m x n x p")
+    s = B.shape[3]
+    if out is None:
+        out = torch.empty((4, p, m, s), dtype=A.dtype, device=A.device)
+    else:
+        _check_tensor(out, "out", prec)
+    need = nat.qt_workspace_size(m, n, s, p, prec)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, A.device)
+    st = nat.qt_tprod(m, n, s, p, A.data_ptr(), B.data_ptr(), out.data_ptr(), prec,
+                      ws.data_ptr(), ws.numel(), _stream(A.device))
+    nat.check(st, "qt_tprod")
+    return out
+
+
+def tprod_backward(A: torch.Tensor, B: torch.Tensor, G: torch.Tensor, precision="fp32",
+                   need_dA: bool = True, need_dB: bool = True):
+    """(dA, dB) = (G * B^H, A^H * G) on the GPU; None for a skipped one."""
+    prec = _prec(precision)
+    for x, nm in ((A, "A"), (B, "B"), (G, "G")):
+        _check_tensor(x, nm, prec)
+    _, p, m, n = A.shape
+    s = B.shape[3]
+    if G.shape != (4, p, m, s):
+        raise ValueError("G must have the shape of A * B")
+    dA = torch.empty_like(A) if need_dA else None
+    dB = torch.empty_like(B) if need_dB else None
+    need = nat.qt_backward_workspace_size(m, n, s, p, prec)
+    ws = workspace(need, A.device)
+    st = nat.qt_tprod_backward(m, n, s, p, A.data_ptr(), B.data_ptr(), G.data_ptr(),
+                               dA.data_ptr() if dA is not None else None,
+                               dB.data_ptr() if dB is not None else None,
+                               prec, ws.data_ptr(), ws.numel(), _stream(A.device))
+    nat.check(st, "qt_tprod_backward")
+    return dA, dB
+
+
+def tprod_batched(As, Bs, precision="fp32", outs=None):
+    """[A_i * B_i] for lists of tensors, in one persistent launch."""
+    prec = _prec(precision)
+    if len(As) != len(Bs) or not As:
+        raise ValueError("need equally many A and B tensors (at least one)")
+    items = []
+    if outs is None:
+        outs = []
+        for A, B in zip(As, Bs):
+            outs.append(torch.empty((4, A.shape[1], A.shape[2], B.shape[3]), dtype=A.dtype,
+                                    device=A.device))
+    for A, B, C in zip(As, Bs, outs):
+        _check_tensor(A, "A", prec)
+        _check_tensor(B, "B", prec)
+        _check_tensor(C, "C", prec)
+        items.append((A.shape[2], A.shape[3], B.shape[3], A.shape[1], A.data_ptr(), B.data_ptr(),
+                      C.data_ptr()))
+    probs = nat.make_problems(items)
+    need = nat.qt_batched_workspace_size(len(items), probs, prec)
+    ws = workspace(need, As[0].device)
+    st = nat.qt_tprod_batched(len(items), probs, prec, ws.data_ptr(), ws.numel(),
+                              _stream(As[0].device))
+    nat.check(st, "qt_tprod_batched")
+    return outs
+
+
+class QTProd(torch.autograd.Function):
+    """C = A * B with the hand-written Fourier-domain backward.
+
+    Gradients are plain real gradients of the four component planes:
+    dL/dA = G * B^H, dL/dB = A^H * G for G = dL/dC.
+    """
+
+    @staticmethod
+    def forward(ctx, A, B, precision="fp32"):
+        ctx.precision = precision
+        ctx.save_for_backward(A, B)
+        return tprod(A.contiguous(), B.contiguous(), precision)
+
+    @staticmethod
+    def backward(ctx, G):
+        A, B = ctx.saved_tensors
+        dA, dB = tprod_backward(A, B, G.contiguous(), ctx.precision,
+                                need_dA=ctx.needs_input_grad[0], need_dB=ctx.needs_input_grad[1])
+        return dA, dB, None
+
+
+def qtprod(A, B, precision="fp32"):
+    """Differentiable T-product (autograd through QTProd)."""
+    return QTProd.apply(A, B, precision)

@@ -1,0 +1,122 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, sizes its workspace as documented and rejects invalid
+arguments on the host before any launch."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2212_14318_amd import _native as nat
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qtprod.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qt_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    names = header_functions()
+    for n in ["qt_tprod", "qt_tprod_batched", "qt_tprod_backward", "qt_workspace_size",
+              "qt_status_string", "qt_tube_fft"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = nat.lib()
+    for name in header_functions():
+        assert hasattr(lib, name), f"{name} declared in qtprod.h but not exported"
+        assert name in nat.SIGNATURES, f"{name} has no Python binding"
+
+
+def test_status_strings():
+    for st in (nat.QT_OK, nat.QT_ERR_INVALID_ARG, nat.QT_ERR_UNSUPPORTED, nat.QT_ERR_ALLOC,
+               nat.QT_ERR_HIP):
+        s = nat.qt_status_string(st)
+        assert s.startswith("QT_")
+    assert "unknown" in nat.qt_status_string(12345)
+    assert nat.qt_version() >= 100
+
+
+def _fourier_bytes(rows, cols, p, esize):
+    ld = (cols + 3) // 4 * 4
+    b = 4 * p * rows * ld * esize
+    return (b + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("m,n,s,p", [(1, 1, 1, 1), (8, 8, 8, 8), (256, 256, 256, 64), (17, 5, 33, 7)])
+def test_workspace_size_formula(m, n, s, p):
+    for prec, es in ((nat.QT_FP32, 4), (nat.QT_SPLIT_BF16, 4), (nat.QT_FP64, 8)):
+        want = _fourier_bytes(m, n, p, es) + _fourier_bytes(n, s, p, es) + _fourier_bytes(m, s, p, es)
+        assert nat.qt_workspace_size(m, n, s, p, prec) == want
+
+
+def test_workspace_size_invalid_is_zero():
+    assert nat.qt_workspace_size(0, 4, 4, 4, nat.QT_FP32) == 0
+    assert nat.qt_workspace_size(4, 4, 4, -1, nat.QT_FP32) == 0
+    assert nat.qt_workspace_size(4, 4, 4, 4, 99) == 0
+
+
+def test_workspace_size_monotone():
+    prev = 0
+    for m in (1, 7, 64, 100, 513):
+        w = nat.qt_workspace_size(m, 33, 21, 12, nat.QT_FP32)
+        assert w > prev
+        prev = w
+
+
+# Fake, never-dereferenced device addresses: every call below must be rejected
+# on the host before the library touches HIP.
+A_, B_, C_, W_ = 0x10000000, 0x20000000, 0x30000000, 0x40000000
+
+
+@pytest.mark.parametrize("args", [
+    (0, 4, 4, 4), (4, 0, 4, 4), (4, 4, 0, 4), (4, 4, 4, 0), (-3, 4, 4, 4),
+])
+def test_tprod_rejects_bad_sizes(args):
+    m, n, s, p = args
+    st = nat.qt_tprod(m, n, s, p, A_, B_, C_, nat.QT_FP32, W_, 1 << 30, None)
+    assert st == nat.QT_ERR_INVALID_ARG
+
+
+def test_tprod_rejects_null_misaligned_aliased_and_small_ws():
+    ws = nat.qt_workspace_size(8, 8, 8, 8, nat.QT_FP32)
+    ok = (8, 8, 8, 8)
+    assert nat.qt_tprod(*ok, None, B_, C_, nat.QT_FP32, W_, ws, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod(*ok, A_, None, C_, nat.QT_FP32, W_, ws, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod(*ok, A_, B_, None, nat.QT_FP32, W_, ws, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod(*ok, A_, B_, C_, nat.QT_FP32, None, ws, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod(*ok, A_ + 4, B_, C_, nat.QT_FP32, W_, ws, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod(*ok, A_, B_, C_ + 8, nat.QT_FP32, W_, ws, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod(*ok, A_, B_, C_, nat.QT_FP32, W_, ws - 1, None) == nat.QT_ERR_INVALID_ARG
+    # C overlapping A, workspace overlapping B
+    assert nat.qt_tprod(*ok, A_, B_, A_ + 256, nat.QT_FP32, W_, ws, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod(*ok, A_, B_, C_, nat.QT_FP32, B_, ws, None) == nat.QT_ERR_INVALID_ARG
+    # unknown precision
+    assert nat.qt_tprod(*ok, A_, B_, C_, 7, W_, ws, None) == nat.QT_ERR_INVALID_ARG
+
+
+def test_tube_fft_rejects_bad_args():
+    assert nat.qt_tube_fft(0, 4, 4, A_, B_, 0, nat.QT_FP32, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tube_fft(4, 4, 4, A_, A_ + 16, 0, nat.QT_FP32, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tube_fft(4, 4, 4, A_, B_, 2, nat.QT_FP32, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tube_fft(4, 4, 4, A_, B_, 0, nat.QT_SPLIT_BF16, None) == nat.QT_ERR_INVALID_ARG
+
+
+def test_prepare_rejects_bad_p():
+    assert nat.qt_prepare(0, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_prepare(nat.QT_MAX_P + 1, None) == nat.QT_ERR_UNSUPPORTED
+
+
+def test_product_path_has_no_oracle_or_fallback():
+    """The package never imports the oracle and has no CPU implementation."""
+    pkg = os.path.join(ROOT, "paper_2212_14318_amd")
+    for f in os.listdir(pkg):
+        if f.endswith(".py"):
+            src = open(os.path.join(pkg, f)).read()
+            assert "oracle" not in src.replace("no fallback", ""), f
+            assert "numpy" not in src, f

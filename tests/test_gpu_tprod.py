@@ -1,0 +1,158 @@
+"""GPU parity of the forward T-product (qt_tprod, qt_tube_fft) against the
+FP64 oracle.  Tolerances: relative Frobenius error <= 1e-5 for the FP32 path
+and <= 1e-13 for the FP64 path (the paper observes ~1e-16 for the fast
+algorithm in FP64; 1e-13 leaves room for the accumulation order)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_2212_14318_amd import _native as nat
+from paper_2212_14318_amd import tprod, tube_fft
+
+from gpu_util import device, rel_err, sample_indices, sampled_rel_err, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+FP64_TOL = 1e-13
+
+
+# ------------------------------------------------------------------ tube FFT
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8, 9, 12, 16, 30, 32, 45, 49, 64, 100, 125, 128])
+def test_tube_fft_matches_numpy(p):
+    rows, cols = 13, 37
+    X = synth.quat_tensor(rows, cols, p, seed=100 + p)
+    Xd = to_dev(X)
+    H = to_np(tube_fft(Xd))
+    want1 = np.fft.fft(X[0] + 1j * X[1], axis=0)
+    want2 = np.fft.fft(X[2] + 1j * X[3], axis=0)
+    want = np.stack([want1.real, want1.imag, want2.real, want2.imag])
+    assert rel_err(H, want) < 2e-6
+    back = to_np(tube_fft(to_dev(want), inverse=True))
+    assert rel_err(back, X) < 2e-6
+
+
+@pytest.mark.parametrize("p", [1, 3, 8, 16, 30, 64])
+def test_tube_fft_fp64(p):
+    X = synth.quat_tensor(5, 9, p, seed=200 + p)
+    H = to_np(tube_fft(to_dev(X, torch.float64), precision="fp64"))
+    w1 = np.fft.fft(X[0] + 1j * X[1], axis=0)
+    w2 = np.fft.fft(X[2] + 1j * X[3], axis=0)
+    assert rel_err(H, np.stack([w1.real, w1.imag, w2.real, w2.imag])) < 1e-14
+
+
+# ------------------------------------------------------------- small configs
+def test_c1_fp64():
+    A, B = synth.config_inputs(1)
+    C = tprod(to_dev(A, torch.float64), to_dev(B, torch.float64), precision="fp64")
+    err = rel_err(to_np(C), oracle.tprod(A, B))
+    print(f"c1 fp64 rel err {err:.3e}")
+    assert err <= FP64_TOL
+
+
+def test_c1_fp32():
+    A, B = synth.config_inputs(1)
+    C = tprod(to_dev(A), to_dev(B))
+    err = rel_err(to_np(C), oracle.tprod(A, B))
+    print(f"c1 fp32 rel err {err:.3e}")
+    assert err <= FP32_TOL
+
+
+# Several GEMM tiles in m and s with ragged tails, several k-chunks with a
+# ragged tail, and every kind of p (odd, even, prime factors 2/3/5/7).
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 7, 8, 12, 16, 30, 32])
+def test_parity_ragged_full(p):
+    m, n, s = 300, 50, 150
+    A = synth.quat_tensor(m, n, p, seed=300 + p)
+    B = synth.quat_tensor(n, s, p, seed=400 + p)
+    C = to_np(tprod(to_dev(A), to_dev(B)))
+    err = rel_err(C, oracle.tprod_faces(A, B))
+    print(f"p={p} rel err {err:.3e}")
+    assert err <= FP32_TOL
+
+
+@pytest.mark.parametrize("p", [45, 64, 100, 128])
+def test_parity_ragged_faces(p):
+    m, n, s = 260, 36, 140
+    A = synth.quat_tensor(m, n, p, seed=500 + p)
+    B = synth.quat_tensor(n, s, p, seed=600 + p)
+    C = to_np(tprod(to_dev(A), to_dev(B)))
+    faces = [0, 1, p // 2, p - 1]
+    err = rel_err(C[:, faces], oracle.tprod_faces(A, B, faces))
+    print(f"p={p} rel err on faces {faces}: {err:.3e}")
+    assert err <= FP32_TOL
+
+
+@pytest.mark.parametrize("m,n,s,p", [(1, 1, 1, 1), (1, 1, 1, 7), (1, 3, 1, 4), (5, 1, 3, 6),
+                                     (2, 2, 2, 2), (129, 17, 65, 3), (128, 16, 64, 4)])
+def test_edge_shapes(m, n, s, p):
+    A = synth.quat_tensor(m, n, p, seed=700 + m + n + s + p)
+    B = synth.quat_tensor(n, s, p, seed=800 + m + n + s + p)
+    ref = oracle.tprod(A, B)
+    C32 = to_np(tprod(to_dev(A), to_dev(B)))
+    assert rel_err(C32, ref) <= FP32_TOL
+    C64 = to_np(tprod(to_dev(A, torch.float64), to_dev(B, torch.float64), precision="fp64"))
+    assert rel_err(C64, ref) <= FP64_TOL
+
+
+def test_p1_is_quaternion_matrix_product():
+    A = synth.quat_tensor(70, 30, 1, seed=901)
+    B = synth.quat_tensor(30, 90, 1, seed=902)
+    C = to_np(tprod(to_dev(A), to_dev(B)))
+    from oracle.quaternion import qmatmul
+    assert rel_err(C[:, 0], qmatmul(A[:, 0], B[:, 0])) <= FP32_TOL
+
+
+def test_identity_tensor_gpu():
+    p, n = 12, 40
+    A = synth.quat_tensor(33, n, p, seed=903)
+    C = to_np(tprod(to_dev(A), to_dev(oracle.identity(n, p))))
+    assert rel_err(C, A) <= FP32_TOL
+
+
+def test_deterministic():
+    A = synth.quat_tensor(200, 64, 16, seed=904)
+    B = synth.quat_tensor(64, 100, 16, seed=905)
+    Ad, Bd = to_dev(A), to_dev(B)
+    C1 = tprod(Ad, Bd).cpu()
+    C2 = tprod(Ad, Bd).cpu()
+    assert torch.equal(C1, C2)
+
+
+def test_nan_propagates():
+    A = synth.quat_tensor(16, 8, 4, seed=906)
+    B = synth.quat_tensor(8, 16, 4, seed=907)
+    A[1, 2, 3, 4] = np.nan
+    C = to_np(tprod(to_dev(A), to_dev(B)))
+    assert np.isnan(C[:, :, 3, :]).all()          # row 3 of every face is poisoned
+    assert np.isfinite(np.delete(C, 3, axis=2)).all()
+
+
+def test_status_errors_raise():
+    A = to_dev(synth.quat_tensor(4, 4, 4, seed=1))
+    with pytest.raises(ValueError):
+        tprod(A, to_dev(synth.quat_tensor(5, 4, 4, seed=2)))
+
+
+# ----------------------------------------------------------- full-size runs
+def test_c2_full_size_sampled():
+    A, B = synth.config_inputs(2)
+    C = to_np(tprod(to_dev(A), to_dev(B)))
+    k, i, j = sample_indices(64, 256, 256, 16, seed=2100, per_face=True)
+    err = sampled_rel_err(C, A, B, k, i, j)
+    print(f"c2 sampled rel err {err:.3e}")
+    assert err <= FP32_TOL
+    full = oracle.tprod_faces(A, B, [0, 33])
+    assert rel_err(C[:, [0, 33]], full) <= FP32_TOL
+
+
+@pytest.mark.parametrize("draw", [1, 2])
+def test_c3_full_size_sampled(draw):
+    A, B = synth.config_inputs(3, draw=draw)
+    C = to_np(tprod(to_dev(A), to_dev(B)))
+    k, i, j = sample_indices(32, 1024, 1024, 12, seed=3100 + draw, per_face=True)
+    err = sampled_rel_err(C, A, B, k, i, j)
+    print(f"c3 draw {draw} sampled rel err {err:.3e}")
+    assert err <= FP32_TOL
