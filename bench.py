@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Benchmark of the fast quaternion T-product on one MI355X.
+
+One step = one whole T-product C = A * B on inputs already resident in HBM:
+forward tube FFT of A and B, coupled facewise products, inverse tube FFT
+(the three stages of qt_tprod, issued through the C-ABI one stage at a time
+so that HIP events on the launch stream time each kernel).
+
+Default workload: A, B of 1024 x 1024 x 32, components i.i.d. N(0, 1)
+(seeds 3000/3001), FP32 path and bf16 hi+lo split path.  `value` is the
+whole-step TFLOP/s-equivalent of the headline precision, with the
+algorithmic count F = 32 m n s p (facewise products; the count of the proof
+of Theorem 5.2 with additions) + 10 p log2(p) (mn + ns + ms) (two complex
+length-p FFTs per quaternion tube, 5 N log2 N each).
+
+Prints progress to stderr and ONE JSON line to stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp32": 157.3, "split_bf16": 2516.6, "split_fp16": 2516.6, "fp64": 78.6}
+PEAK_HBM_GBPS = 8000.0
+
+WORKLOADS = {
+    "c2": dict(cfg=2, desc="A, B 256x256x64 quaternion, components U[0,1) (seeds 2000/2001)"),
+    "c3": dict(cfg=3, desc="A, B 1024x1024x32 quaternion, components N(0,1) (seeds 3000/3001)"),
+    "c5": dict(cfg=5, desc="A 512x64x100, B 64x512x100 quaternion, components N(0,1) "
+                           "(seeds 5000/5001)"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def flops(m, n, s, p):
+    f_gemm = 32.0 * m * n * s * p
+    f_fft = 10.0 * p * math.log2(p) * (m * n + n * s + m * s) if p > 1 else 0.0
+    return f_gemm, f_fft
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--precisions", default="split_bf16,fp32",
+                    help="comma list; the first is the headline `value`")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; the T-product runs on a single "
+              "MI355X and --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2212_14318_amd import _native as nat
+    from paper_2212_14318_amd import ops
+
+    if not torch.cuda.is_available():
+        print("bench.py: no ROCm GPU visible", file=sys.stderr)
+        sys.exit(3)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    sh = stream.cuda_stream
+
+    wl = WORKLOADS[args.workload]
+    cfg = wl["cfg"]
+    t0 = time.time()
+    inputs = synth.config_inputs(cfg)
+    A64, B64 = inputs[0], inputs[1]
+    _, p, m, n = A64.shape
+    s = B64.shape[3]
+    log(f"[bench] inputs {args.workload} m={m} n={n} s={s} p={p} drawn in {time.time() - t0:.1f}s")
+    A = torch.from_numpy(A64).to(dev, torch.float32)
+    B = torch.from_numpy(B64).to(dev, torch.float32)
+    lda, ldb = nat.qt_fourier_ld(n), nat.qt_fourier_ld(s)
+    Ah = torch.empty((4, p, m, lda), dtype=torch.float32, device=dev)
+    Bh = torch.empty((4, p, n, ldb), dtype=torch.float32, device=dev)
+    Ch = torch.empty((4, p, m, ldb), dtype=torch.float32, device=dev)
+    C = torch.empty((4, p, m, s), dtype=torch.float32, device=dev)
+    f_gemm, f_fft = flops(m, n, s, p)
+    F = f_gemm + f_fft
+    fft_fwd_bytes = 32.0 * p * (m * n + n * s)       # read + write 16 B per quaternion
+    fft_inv_bytes = 32.0 * p * (m * s)
+
+    if args.copy_calib_mib:
+        nb = args.copy_calib_mib << 20
+        src = torch.empty(nb // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {nb} bytes read + {nb} bytes written")
+        del src, dst
+
+    def stage_calls(prec_id, ev):
+        st = nat.qt_tube_fft(m, n, p, A.data_ptr(), n, Ah.data_ptr(), lda, 0, nat.QT_FP32, sh)
+        nat.check(st, "qt_tube_fft(A)")
+        st = nat.qt_tube_fft(n, s, p, B.data_ptr(), s, Bh.data_ptr(), ldb, 0, nat.QT_FP32, sh)
+        nat.check(st, "qt_tube_fft(B)")
+        ev[0].record(stream)
+        st = nat.qt_fourier_tprod(m, n, s, p, Ah.data_ptr(), lda, Bh.data_ptr(), ldb,
+                                  Ch.data_ptr(), ldb, prec_id, sh)
+        nat.check(st, "qt_fourier_tprod")
+        ev[1].record(stream)
+        st = nat.qt_tube_fft(m, s, p, Ch.data_ptr(), ldb, C.data_ptr(), s, 1, nat.QT_FP32, sh)
+        nat.check(st, "qt_tube_fft(C^, inverse)")
+
+    results = {}
+    precs = [x for x in args.precisions.split(",") if x]
+    for prec in precs:
+        prec_id = nat.PRECISIONS[prec]
+        # check the staged path against the single entry point once (untimed)
+        ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        try:
+            C_ref = ops.tprod(A, B, precision=prec)
+        except nat.QtError as e:
+            log(f"[bench] precision {prec} not available: {e}")
+            continue
+        stage_calls(prec_id, ev0)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(C, C_ref))
+        del C_ref
+        for _ in range(args.warmup):
+            stage_calls(prec_id, ev0)
+        torch.cuda.synchronize()
+        marks = []
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e[0].record(stream)
+            stage_calls(prec_id, (e[1], e[2]))
+            e[3].record(stream)
+            marks.append(e)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        fwd = [mk[0].elapsed_time(mk[1]) for mk in marks]
+        gem = [mk[1].elapsed_time(mk[2]) for mk in marks]
+        inv = [mk[2].elapsed_time(mk[3]) for mk in marks]
+        ms_step = wall * 1e3 / args.steps
+        t_gemm = sum(gem) / len(gem)
+        t_fwd = sum(fwd) / len(fwd)
+        t_inv = sum(inv) / len(inv)
+        # sampled error against the FP64 oracle is computed after all GPU timing
+        results[prec] = dict(
+            ms_per_step=ms_step, tflops_equiv=F / (ms_step * 1e-3) / 1e12,
+            gemm_ms=t_gemm, fft_fwd_ms=t_fwd, fft_inv_ms=t_inv,
+            gemm_tflops=f_gemm / (t_gemm * 1e-3) / 1e12,
+            fft_fwd_gbps=fft_fwd_bytes / (t_fwd * 1e-3) / 1e9,
+            fft_inv_gbps=fft_inv_bytes / (t_inv * 1e-3) / 1e9,
+            staged_equals_qt_tprod=same,
+            C=C.cpu().numpy(),
+        )
+        log(f"[bench] {prec}: {ms_step:.3f} ms/step  {results[prec]['tflops_equiv']:.1f} TFLOP/s-equiv"
+            f"  gemm {t_gemm:.3f} ms ({results[prec]['gemm_tflops']:.1f} TF)"
+            f"  fft {t_fwd:.3f}+{t_inv:.3f} ms  staged==qt_tprod: {same}")
+
+    if not results:
+        print("bench.py: no precision could run", file=sys.stderr)
+        sys.exit(4)
+
+    # ---- accuracy: sampled relative Frobenius error vs the FP64 oracle ----
+    import oracle
+    rng = np.random.Generator(np.random.PCG64(31337))
+    per_face = 12
+    kk = np.repeat(np.arange(p), per_face)
+    ii = rng.integers(0, m, kk.size)
+    jj = rng.integers(0, s, kk.size)
+    ref = oracle.tprod_entries(A64, B64, kk, ii, jj)
+    for prec, r in results.items():
+        got = r.pop("C")[:, kk, ii, jj].astype(np.float64)
+        r["rel_err"] = float(np.sqrt(np.sum((got - ref) ** 2)) / np.sqrt(np.sum(ref ** 2)))
+        log(f"[bench] {prec}: sampled rel. Frobenius error vs FP64 oracle = {r['rel_err']:.3e}")
+
+    # ---- CPU baseline: the oracle itself on a bounded sample of the job ----
+    cpu = None
+    if not args.no_cpu_baseline:
+        import threadpoolctl
+        np.ones((8, 8)) @ np.ones((8, 8))
+        threads = max([d.get("num_threads", 1) for d in threadpoolctl.threadpool_info()] or [1])
+        faces_done = 0
+        t0 = time.perf_counter()
+        while faces_done < p and time.perf_counter() - t0 < args.cpu_seconds:
+            oracle.tprod_faces(A64, B64, [faces_done])
+            faces_done += 1
+        t_cpu = time.perf_counter() - t0
+        frac = faces_done / p
+        cpu = {"value": F * frac / t_cpu / 1e12, "unit": "TFLOP/s-equiv", "cores": int(threads),
+               "kind": "oracle",
+               "sample": f"{faces_done} of {p} output faces of the same workload (FP64 "
+                         f"definition, block-row form), {t_cpu:.1f} s; value = F x {faces_done}/{p} / time"}
+        log(f"[bench] oracle CPU baseline: {cpu['value']:.4g} TFLOP/s-equiv on {threads} threads "
+            f"({faces_done} faces in {t_cpu:.1f}s)")
+
+    head = precs[0] if precs[0] in results else next(iter(results))
+    r = results[head]
+    peak = PEAK_TFLOPS[head]
+    roof = {"bound": "mfma", "achieved": round(r["gemm_tflops"], 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(r["gemm_tflops"] / peak, 4), "traffic": None,
+            "kernel": "facewise coupled product (qt_fourier_tprod)",
+            "algorithmic_flops_per_launch": f_gemm}
+    if head.startswith("split"):
+        roof["issued_frac"] = round(3 * r["gemm_tflops"] / peak, 4)
+    dtype = {"fp32": "f32", "split_bf16": "bf16x3-split/f32-acc", "split_fp16": "fp16x3-split/f32-acc",
+             "fp64": "f64"}[head]
+    out = {
+        "metric": "T-product TFLOP/s-equiv & % roofline, split-BF16 vs FP32 at stated rel. error",
+        "value": round(r["tflops_equiv"], 3),
+        "unit": "TFLOP/s-equiv",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dtype, "data": "synthetic",
+        "config": {"workload": wl["desc"], "m": m, "n": n, "s": s, "p": p, "precision": head,
+                   "flops_per_step": F},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "per_precision": {k: {kk2: (round(v, 5) if isinstance(v, float) else v)
+                              for kk2, v in d.items()} for k, d in results.items()},
+        "fft_roofline": {"bound": "hbm", "fwd_achieved": round(r["fft_fwd_gbps"], 1),
+                         "inv_achieved": round(r["fft_inv_gbps"], 1), "peak": PEAK_HBM_GBPS,
+                         "unit": "GB/s", "fwd_frac": round(r["fft_fwd_gbps"] / PEAK_HBM_GBPS, 4),
+                         "inv_frac": round(r["fft_inv_gbps"] / PEAK_HBM_GBPS, 4)},
+    }
+    if "fp32" in results and head != "fp32":
+        out["speedup_vs_fp32"] = round(results["fp32"]["ms_per_step"] / r["ms_per_step"], 3)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -91,18 +91,35 @@ const char* qt_status_string(int status);
  * QT_ERR_UNSUPPORTED, QT_ERR_ALLOC or QT_ERR_HIP. */
 int qt_prepare(int p, hipStream_t stream);
 
+/* Row stride (in reals) that qt_tprod uses for its Fourier-domain tensors:
+ * cols rounded up to a multiple of 4.  Any ld >= cols that is a multiple of 4
+ * is accepted by qt_fourier_tprod. */
+int qt_fourier_ld(int cols);
+
 /* Tube FFT of one quaternion tensor X (rows x cols x p) -- the block
  * diagonalisation of bcirc(X) of Theorem 4.4, in the plain-DFT convention:
  *   inverse = 0:  Xh[c][f] = sum_k X[c][k] w^(f k), w = exp(-2 pi i / p), applied
  *                 to the complex parts X1 = (plane 0, plane 1) and
  *                 X2 = (plane 2, plane 3) separately;
  *   inverse = 1:  the inverse transform, with the factor 1/p.
- * Output Xh has the same dense layout [4][p][rows][cols], planes
- * (Re X1^, Im X1^, Re X2^, Im X2^).  (The paper's transform of Theorem 4.4 is
- * fft(conj X) = conj(X1^[-f]) - X2^[f] j in these terms.)  X and Xh must not
- * overlap.  precision: QT_FP32 (float) or QT_FP64 (double). */
-int qt_tube_fft(int rows, int cols, int p, const void* X, void* Xh, int inverse,
-                int precision, hipStream_t stream);
+ * X is read as [4][p][rows][ldx] and Xh written as [4][p][rows][ldh]
+ * (ldx, ldh >= cols; entries beyond cols are neither read nor written);
+ * Xh planes are (Re X1^, Im X1^, Re X2^, Im X2^).  The paper's transform of
+ * Theorem 4.4 is fft(conj X) = conj(X1^[-f]) - X2^[f] j in these terms.
+ * X and Xh must not overlap.  precision: QT_FP32 (float) or QT_FP64 (double);
+ * the split precisions use the FP32 transform, so they are accepted as FP32. */
+int qt_tube_fft(int rows, int cols, int p, const void* X, int ldx, void* Xh, int ldh,
+                int inverse, int precision, hipStream_t stream);
+
+/* Step 2 alone, for Fourier-domain-resident chains: for every frequency f,
+ *   C1^[f] = A1^[f] B1^[f] - A2^[f] conj(B2^[-f]),
+ *   C2^[f] = A1^[f] B2^[f] + A2^[f] conj(B1^[-f])   (Theorem 5.1, Remark 5.1),
+ * on tensors produced by qt_tube_fft: Ah [4][p][m][lda], Bh [4][p][n][ldb],
+ * Ch [4][p][m][ldc] (ldc >= s, entries beyond s untouched).  For the float
+ * precisions lda, ldb, ldc must be multiples of 4 (16-byte rows).
+ * qt_tube_fft(inverse = 1) of Ch is then A * B.  No workspace. */
+int qt_fourier_tprod(int m, int n, int s, int p, const void* Ah, int lda, const void* Bh,
+                     int ldb, void* Ch, int ldc, int precision, hipStream_t stream);
 
 /* Workspace bytes needed by qt_tprod for these sizes and precision
  * (0 if an argument is invalid).  Holds the Fourier-domain tensors

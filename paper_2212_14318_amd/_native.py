@@ -40,7 +40,9 @@ SIGNATURES = {
     "qt_version": (_I, []),
     "qt_status_string": (ctypes.c_char_p, [_I]),
     "qt_prepare": (_I, [_I, _P]),
-    "qt_tube_fft": (_I, [_I, _I, _I, _P, _P, _I, _I, _P]),
+    "qt_fourier_ld": (_I, [_I]),
+    "qt_tube_fft": (_I, [_I, _I, _I, _P, _I, _P, _I, _I, _I, _P]),
+    "qt_fourier_tprod": (_I, [_I, _I, _I, _I, _P, _I, _P, _I, _P, _I, _I, _P]),
     "qt_workspace_size": (_SZ, [_I, _I, _I, _I, _I]),
     "qt_tprod": (_I, [_I, _I, _I, _I, _P, _P, _P, _I, _P, _SZ, _P]),
     "qt_batched_workspace_size": (_SZ, [_I, ctypes.POINTER(qt_problem), _I]),
@@ -94,8 +96,16 @@ def qt_prepare(p: int, stream: int = 0) -> int:
     return lib().qt_prepare(p, stream)
 
 
-def qt_tube_fft(rows, cols, p, X, Xh, inverse, precision, stream=0) -> int:
-    return lib().qt_tube_fft(rows, cols, p, X, Xh, inverse, precision, stream)
+def qt_fourier_ld(cols: int) -> int:
+    return lib().qt_fourier_ld(cols)
+
+
+def qt_tube_fft(rows, cols, p, X, ldx, Xh, ldh, inverse, precision, stream=0) -> int:
+    return lib().qt_tube_fft(rows, cols, p, X, ldx, Xh, ldh, inverse, precision, stream)
+
+
+def qt_fourier_tprod(m, n, s, p, Ah, lda, Bh, ldb, Ch, ldc, precision, stream=0) -> int:
+    return lib().qt_fourier_tprod(m, n, s, p, Ah, lda, Bh, ldb, Ch, ldc, precision, stream)
 
 
 def qt_workspace_size(m: int, n: int, s: int, p: int, precision: int) -> int:

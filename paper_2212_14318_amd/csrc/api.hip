@@ -143,26 +143,57 @@ int qt_prepare(int p, hipStream_t stream) {
     return get_plan(p, stream, &tw);
 }
 
-int qt_tube_fft(int rows, int cols, int p, const void* X, void* Xh, int inverse, int precision,
-                hipStream_t stream) {
-    if (precision != QT_FP32 && precision != QT_FP64) return QT_ERR_INVALID_ARG;
+int qt_fourier_ld(int cols) { return cols < 1 ? 0 : (int)qt::fourier_ld(cols); }
+
+int qt_tube_fft(int rows, int cols, int p, const void* X, int ldx, void* Xh, int ldh, int inverse,
+                int precision, hipStream_t stream) {
+    if (!valid_precision(precision)) return QT_ERR_INVALID_ARG;
     if (!dims_ok(rows, cols, p) || !X || !Xh || !aligned16(X) || !aligned16(Xh))
         return QT_ERR_INVALID_ARG;
+    if (ldx < cols || ldh < cols || !dims_ok(rows, ldx, p) || !dims_ok(rows, ldh, p))
+        return QT_ERR_INVALID_ARG;
     if (inverse != 0 && inverse != 1) return QT_ERR_INVALID_ARG;
-    const size_t bytes = tensor_bytes(rows, cols, p, precision);
-    if (overlaps(X, bytes, Xh, bytes)) return QT_ERR_INVALID_ARG;
+    if (overlaps(X, tensor_bytes(rows, ldx, p, precision), Xh, tensor_bytes(rows, ldh, p, precision)))
+        return QT_ERR_INVALID_ARG;
     if (!p_supported(p, precision)) return QT_ERR_UNSUPPORTED;
     Twiddles tw;
     int st = get_plan(p, stream, &tw);
     if (st != QT_OK) return st;
     hipError_t e;
     if (precision == QT_FP64) {
-        FftJob<double> j{(const double*)X, (double*)Xh, rows, cols, cols, cols};
+        FftJob<double> j{(const double*)X, (double*)Xh, rows, cols, ldx, ldh};
         e = qt::launch_tube_fft<double>(p, inverse != 0, &j, 1, tw, stream);
     } else {
-        FftJob<float> j{(const float*)X, (float*)Xh, rows, cols, cols, cols};
+        FftJob<float> j{(const float*)X, (float*)Xh, rows, cols, ldx, ldh};
         e = qt::launch_tube_fft<float>(p, inverse != 0, &j, 1, tw, stream);
     }
+    return e == hipSuccess ? QT_OK : QT_ERR_HIP;
+}
+
+int qt_fourier_tprod(int m, int n, int s, int p, const void* Ah, int lda, const void* Bh, int ldb,
+                     void* Ch, int ldc, int precision, hipStream_t stream) {
+    if (!valid_precision(precision)) return QT_ERR_INVALID_ARG;
+    if (!dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p)) return QT_ERR_INVALID_ARG;
+    if (!Ah || !Bh || !Ch || !aligned16(Ah) || !aligned16(Bh) || !aligned16(Ch))
+        return QT_ERR_INVALID_ARG;
+    if (lda < n || ldb < s || ldc < s) return QT_ERR_INVALID_ARG;
+    if (precision != QT_FP64 && ((lda | ldb | ldc) & 3)) return QT_ERR_INVALID_ARG;
+    if (!dims_ok(m, lda, p) || !dims_ok(n, ldb, p) || !dims_ok(m, ldc, p)) return QT_ERR_INVALID_ARG;
+    const size_t cb = tensor_bytes(m, ldc, p, precision);
+    if (overlaps(Ch, cb, Ah, tensor_bytes(m, lda, p, precision)) ||
+        overlaps(Ch, cb, Bh, tensor_bytes(n, ldb, p, precision)))
+        return QT_ERR_INVALID_ARG;
+    hipError_t e;
+    if (precision == QT_FP64) {
+        FacewiseArgs<double> fa{(const double*)Ah, (const double*)Bh, (double*)Ch, m, n, s, p,
+                                lda, ldb, ldc};
+        e = qt::launch_facewise_f64(fa, stream);
+    } else {
+        FacewiseArgs<float> fa{(const float*)Ah, (const float*)Bh, (float*)Ch, m, n, s, p,
+                               lda, ldb, ldc};
+        e = qt::launch_facewise_f32(fa, precision, stream);
+    }
+    if (e == hipErrorNotSupported) return QT_ERR_UNSUPPORTED;
     return e == hipSuccess ? QT_OK : QT_ERR_HIP;
 }
 

@@ -45,15 +45,46 @@ def workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
-def tube_fft(X: torch.Tensor, inverse: bool = False, precision="fp32") -> torch.Tensor:
-    """Tube FFT of a quaternion tensor (block diagonalisation of bcirc(X))."""
+def tube_fft(X: torch.Tensor, inverse: bool = False, precision="fp32", cols=None,
+             out: torch.Tensor | None = None) -> torch.Tensor:
+    """Tube FFT of a quaternion tensor (block diagonalisation of bcirc(X)).
+
+    X has shape (4, p, rows, ld); the first `cols` (default ld) columns are
+    transformed.  `out` may have a different (padded) last dimension.
+    """
     prec = _prec(precision)
     _check_tensor(X, "X", prec)
-    _, p, rows, cols = X.shape
-    out = torch.empty_like(X)
-    st = nat.qt_tube_fft(rows, cols, p, X.data_ptr(), out.data_ptr(), int(bool(inverse)), prec,
-                         _stream(X.device))
+    _, p, rows, ldx = X.shape
+    cols = ldx if cols is None else cols
+    if out is None:
+        out = torch.empty_like(X)
+    else:
+        _check_tensor(out, "out", prec)
+    st = nat.qt_tube_fft(rows, cols, p, X.data_ptr(), ldx, out.data_ptr(), out.shape[3],
+                         int(bool(inverse)), prec, _stream(X.device))
     nat.check(st, "qt_tube_fft")
+    return out
+
+
+def fourier_tprod(Ah: torch.Tensor, Bh: torch.Tensor, n: int, s: int, precision="fp32",
+                  out: torch.Tensor | None = None) -> torch.Tensor:
+    """Coupled facewise product of Fourier-domain tensors (step 2 alone).
+
+    Ah: (4, p, m, lda) holding n valid columns, Bh: (4, p, n, ldb) holding s
+    valid columns; returns Ch (4, p, m, ldc) with s valid columns.
+    """
+    prec = _prec(precision)
+    _check_tensor(Ah, "Ah", prec)
+    _check_tensor(Bh, "Bh", prec)
+    _, p, m, lda = Ah.shape
+    ldb = Bh.shape[3]
+    if out is None:
+        out = torch.empty((4, p, m, ldb), dtype=Ah.dtype, device=Ah.device)
+    else:
+        _check_tensor(out, "out", prec)
+    st = nat.qt_fourier_tprod(m, n, s, p, Ah.data_ptr(), lda, Bh.data_ptr(), ldb, out.data_ptr(),
+                              out.shape[3], prec, _stream(Ah.device))
+    nat.check(st, "qt_fourier_tprod")
     return out
 
 

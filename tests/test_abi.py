@@ -101,10 +101,24 @@ def test_tprod_rejects_null_misaligned_aliased_and_small_ws():
 
 
 def test_tube_fft_rejects_bad_args():
-    assert nat.qt_tube_fft(0, 4, 4, A_, B_, 0, nat.QT_FP32, None) == nat.QT_ERR_INVALID_ARG
-    assert nat.qt_tube_fft(4, 4, 4, A_, A_ + 16, 0, nat.QT_FP32, None) == nat.QT_ERR_INVALID_ARG
-    assert nat.qt_tube_fft(4, 4, 4, A_, B_, 2, nat.QT_FP32, None) == nat.QT_ERR_INVALID_ARG
-    assert nat.qt_tube_fft(4, 4, 4, A_, B_, 0, nat.QT_SPLIT_BF16, None) == nat.QT_ERR_INVALID_ARG
+    F = nat.QT_FP32
+    assert nat.qt_tube_fft(0, 4, 4, A_, 4, B_, 4, 0, F, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tube_fft(4, 4, 4, A_, 4, A_ + 16, 4, 0, F, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tube_fft(4, 4, 4, A_, 4, B_, 4, 2, F, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tube_fft(4, 4, 4, A_, 3, B_, 4, 0, F, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tube_fft(4, 4, 4, A_, 4, B_, 3, 0, F, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tube_fft(4, 4, 4, A_, 4, B_, 4, 0, 9, None) == nat.QT_ERR_INVALID_ARG
+
+
+def test_fourier_tprod_rejects_bad_args():
+    F = nat.QT_FP32
+    ok = (8, 8, 8, 8)
+    assert nat.qt_fourier_tprod(*ok, A_, 6, B_, 8, C_, 8, F, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_fourier_tprod(*ok, A_, 8, B_, 8, C_, 7, F, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_fourier_tprod(*ok, A_, 10, B_, 8, C_, 8, F, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_fourier_tprod(*ok, A_, 8, B_, 8, A_, 8, F, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_fourier_tprod(0, 8, 8, 8, A_, 8, B_, 8, C_, 8, F, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_fourier_ld(5) == 8 and nat.qt_fourier_ld(8) == 8 and nat.qt_fourier_ld(0) == 0
 
 
 def test_prepare_rejects_bad_p():
