@@ -238,7 +238,7 @@ def main():
                    "flops_per_step": F},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "per_precision": {k: {kk2: (round(v, 5) if isinstance(v, float) else v)
+        "per_precision": {k: {kk2: (float(f"{v:.5g}") if isinstance(v, float) else v)
                               for kk2, v in d.items()} for k, d in results.items()},
         "fft_roofline": {"bound": "hbm", "fwd_achieved": round(r["fft_fwd_gbps"], 1),
                          "inv_achieved": round(r["fft_inv_gbps"], 1), "peak": PEAK_HBM_GBPS,
