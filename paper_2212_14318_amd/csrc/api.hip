@@ -91,6 +91,17 @@ int get_plan(int p, hipStream_t stream, Twiddles* out) {
 
 // ------------------------------------------------------------- forward path
 template <typename T>
+hipError_t facewise(const FacewiseArgs<T>& fa, int prec, hipStream_t stream) {
+    if constexpr (sizeof(T) == 8) return qt::launch_facewise_f64(fa, stream);
+    else return qt::launch_facewise_f32(fa, prec, stream);
+}
+
+int hip_status(hipError_t e) {
+    if (e == hipSuccess) return QT_OK;
+    return e == hipErrorNotSupported ? QT_ERR_UNSUPPORTED : QT_ERR_HIP;
+}
+
+template <typename T>
 int run_tprod(int m, int n, int s, int p, const T* A, const T* B, T* C, int prec, char* ws,
               hipStream_t stream) {
     Twiddles tw;
@@ -107,16 +118,89 @@ int run_tprod(int m, int n, int s, int p, const T* A, const T* B, T* C, int prec
 
     // step 2: coupled facewise products
     FacewiseArgs<T> fa{Ah, Bh, Ch, m, n, s, p, lda, ldb, ldc};
-    hipError_t e;
-    if constexpr (sizeof(T) == 8) e = qt::launch_facewise_f64(fa, stream);
-    else e = qt::launch_facewise_f32(fa, prec, stream);
-    if (e == hipErrorNotSupported) return QT_ERR_UNSUPPORTED;
-    if (e != hipSuccess) return QT_ERR_HIP;
+    st = hip_status(facewise<T>(fa, prec, stream));
+    if (st != QT_OK) return st;
 
     // step 3: inverse tube FFT of C^ into C
     FftJob<T> inv[1] = {{Ch, C, m, s, ldc, s}};
     if (qt::launch_tube_fft<T>(p, true, inv, 1, tw, stream) != hipSuccess) return QT_ERR_HIP;
     return QT_OK;
+}
+
+// ------------------------------------------------------------ backward path
+// Workspace regions of the backward pass (each 256-byte aligned):
+//   Y  = B^H (s x n x p, dense)      Z  = A^H (n x m x p, dense)
+//   G^ (m x s, row stride ld(s))     Y^ (s x n, ld(n))     Z^ (n x m, ld(m))
+//   dA^ (m x n, ld(n))               dB^ (n x s, ld(s))
+struct BackwardLayout {
+    size_t y, z, gh, yh, zh, dah, dbh, total;
+};
+
+BackwardLayout backward_layout(long m, long n, long s, long p, int prec) {
+    BackwardLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
+    L.y = take(tensor_bytes(s, n, p, prec));
+    L.z = take(tensor_bytes(n, m, p, prec));
+    L.gh = take(fourier_bytes(m, s, p, prec));
+    L.yh = take(fourier_bytes(s, n, p, prec));
+    L.zh = take(fourier_bytes(n, m, p, prec));
+    L.dah = take(fourier_bytes(m, n, p, prec));
+    L.dbh = take(fourier_bytes(n, s, p, prec));
+    L.total = off;
+    return L;
+}
+
+// dA = G * B^H and dB = A^H * G: transpose-conjugate B and A, one FFT of G
+// shared by both products (it is the left operand of the first and the right
+// operand of the second, with the same Fourier layout), two coupled facewise
+// products, one inverse FFT launch for both results.
+template <typename T>
+int run_backward(int m, int n, int s, int p, const T* A, const T* B, const T* G, T* dA, T* dB,
+                 int prec, char* ws, hipStream_t stream) {
+    Twiddles tw;
+    int st = get_plan(p, stream, &tw);
+    if (st != QT_OK) return st;
+    const BackwardLayout L = backward_layout(m, n, s, p, prec);
+    const int ldm = (int)qt::fourier_ld(m), ldn = (int)qt::fourier_ld(n), lds = (int)qt::fourier_ld(s);
+    T* Y = reinterpret_cast<T*>(ws + L.y);
+    T* Z = reinterpret_cast<T*>(ws + L.z);
+    T* Gh = reinterpret_cast<T*>(ws + L.gh);
+    T* Yh = reinterpret_cast<T*>(ws + L.yh);
+    T* Zh = reinterpret_cast<T*>(ws + L.zh);
+    T* dAh = reinterpret_cast<T*>(ws + L.dah);
+    T* dBh = reinterpret_cast<T*>(ws + L.dbh);
+
+    qt::ConjTJob<T> cj[2];
+    int ncj = 0;
+    if (dA) cj[ncj++] = qt::ConjTJob<T>{B, Y, n, s, p, 0};
+    if (dB) cj[ncj++] = qt::ConjTJob<T>{A, Z, m, n, p, 0};
+    st = hip_status(qt::launch_conj_transpose<T>(cj, ncj, stream));
+    if (st != QT_OK) return st;
+
+    FftJob<T> f1[2] = {{G, Gh, m, s, s, lds}, {Y, Yh, s, n, n, ldn}};
+    st = hip_status(qt::launch_tube_fft<T>(p, false, f1, dA ? 2 : 1, tw, stream));
+    if (st != QT_OK) return st;
+    if (dB) {
+        FftJob<T> f2[1] = {{Z, Zh, n, m, m, ldm}};
+        st = hip_status(qt::launch_tube_fft<T>(p, false, f2, 1, tw, stream));
+        if (st != QT_OK) return st;
+    }
+    if (dA) {
+        FacewiseArgs<T> fa{Gh, Yh, dAh, m, s, n, p, lds, ldn, ldn};
+        st = hip_status(facewise<T>(fa, prec, stream));
+        if (st != QT_OK) return st;
+    }
+    if (dB) {
+        FacewiseArgs<T> fb{Zh, Gh, dBh, n, m, s, p, ldm, lds, lds};
+        st = hip_status(facewise<T>(fb, prec, stream));
+        if (st != QT_OK) return st;
+    }
+    FftJob<T> inv[2];
+    int ninv = 0;
+    if (dA) inv[ninv++] = FftJob<T>{dAh, dA, m, n, ldn, n};
+    if (dB) inv[ninv++] = FftJob<T>{dBh, dB, n, s, lds, s};
+    return hip_status(qt::launch_tube_fft<T>(p, true, inv, ninv, tw, stream));
 }
 
 }  // namespace
@@ -238,16 +322,38 @@ int qt_tprod_batched(int count, const qt_problem* probs, int precision, void* ws
 }
 
 size_t qt_backward_workspace_size(int m, int n, int s, int p, int precision) {
-    (void)m; (void)n; (void)s; (void)p; (void)precision;
-    return 0;
+    if (!valid_precision(precision) || !dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p))
+        return 0;
+    return backward_layout(m, n, s, p, precision).total;
 }
 
 int qt_tprod_backward(int m, int n, int s, int p, const void* A, const void* B, const void* G,
                       void* dA, void* dB, int precision, void* ws, size_t ws_bytes,
                       hipStream_t stream) {
-    (void)m; (void)n; (void)s; (void)p; (void)A; (void)B; (void)G; (void)dA; (void)dB;
-    (void)precision; (void)ws; (void)ws_bytes; (void)stream;
-    return QT_ERR_UNSUPPORTED;
+    if (!valid_precision(precision)) return QT_ERR_INVALID_ARG;
+    if (!dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p)) return QT_ERR_INVALID_ARG;
+    if (!A || !B || !G || !ws) return QT_ERR_INVALID_ARG;
+    if (!aligned16(A) || !aligned16(B) || !aligned16(G) || !aligned16(ws) ||
+        (dA && !aligned16(dA)) || (dB && !aligned16(dB)))
+        return QT_ERR_INVALID_ARG;
+    const size_t need = qt_backward_workspace_size(m, n, s, p, precision);
+    if (ws_bytes < need) return QT_ERR_INVALID_ARG;
+    const size_t ab = tensor_bytes(m, n, p, precision), bb = tensor_bytes(n, s, p, precision);
+    const size_t gb = tensor_bytes(m, s, p, precision);
+    const void* ins[4] = {A, B, G, ws};
+    const size_t insz[4] = {ab, bb, gb, need};
+    for (int q = 0; q < 4; ++q) {
+        if (dA && overlaps(dA, ab, ins[q], insz[q])) return QT_ERR_INVALID_ARG;
+        if (dB && overlaps(dB, bb, ins[q], insz[q])) return QT_ERR_INVALID_ARG;
+    }
+    if (dA && dB && overlaps(dA, ab, dB, bb)) return QT_ERR_INVALID_ARG;
+    if (!p_supported(p, precision)) return QT_ERR_UNSUPPORTED;
+    if (!dA && !dB) return QT_OK;
+    if (precision == QT_FP64)
+        return run_backward<double>(m, n, s, p, (const double*)A, (const double*)B, (const double*)G,
+                                    (double*)dA, (double*)dB, precision, (char*)ws, stream);
+    return run_backward<float>(m, n, s, p, (const float*)A, (const float*)B, (const float*)G,
+                               (float*)dA, (float*)dB, precision, (char*)ws, stream);
 }
 
 }  // extern "C"

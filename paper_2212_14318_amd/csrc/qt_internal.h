@@ -63,4 +63,18 @@ struct FacewiseArgs {
 hipError_t launch_facewise_f32(const FacewiseArgs<float>& a, int precision, hipStream_t stream);
 hipError_t launch_facewise_f64(const FacewiseArgs<double>& a, hipStream_t stream);
 
+// Tensor conjugate transpose job: src is rows x cols x p ([4][p][rows][cols]),
+// dst is cols x rows x p.  planes_faces is filled in by the launcher.
+template <typename T>
+struct ConjTJob {
+    const T* src;
+    T* dst;
+    int rows, cols, p;
+    int planes_faces;
+};
+
+// dst = src^H for one or two jobs in one launch.
+template <typename T>
+hipError_t launch_conj_transpose(const ConjTJob<T>* jobs, int njobs, hipStream_t stream);
+
 }  // namespace qt

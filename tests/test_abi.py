@@ -134,3 +134,32 @@ def test_product_path_has_no_oracle_or_fallback():
             src = open(os.path.join(pkg, f)).read()
             assert "oracle" not in src.replace("no fallback", ""), f
             assert "numpy" not in src, f
+
+
+def _tensor_bytes(rows, cols, p, esize):
+    return (4 * p * rows * cols * esize + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("m,n,s,p", [(8, 8, 8, 8), (512, 64, 512, 100), (5, 3, 7, 2)])
+def test_backward_workspace_formula(m, n, s, p):
+    for prec, es in ((nat.QT_FP32, 4), (nat.QT_FP64, 8)):
+        want = (_tensor_bytes(s, n, p, es) + _tensor_bytes(n, m, p, es) + _fourier_bytes(m, s, p, es)
+                + _fourier_bytes(s, n, p, es) + _fourier_bytes(n, m, p, es)
+                + _fourier_bytes(m, n, p, es) + _fourier_bytes(n, s, p, es))
+        assert nat.qt_backward_workspace_size(m, n, s, p, prec) == want
+
+
+def test_backward_rejects_bad_args():
+    G_, dA_, dB_ = 0x50000000, 0x60000000, 0x70000000
+    ws = nat.qt_backward_workspace_size(8, 8, 8, 8, nat.QT_FP32)
+    ok = (8, 8, 8, 8)
+    F = nat.QT_FP32
+    assert nat.qt_tprod_backward(*ok, None, B_, G_, dA_, dB_, F, W_, ws, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_backward(*ok, A_, B_, None, dA_, dB_, F, W_, ws, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_backward(*ok, A_, B_, G_, dA_, dB_, F, W_, ws - 1, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_backward(*ok, A_, B_, G_, A_, dB_, F, W_, ws, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_backward(*ok, A_, B_, G_, dA_, G_ + 64, F, W_, ws, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_backward(*ok, A_, B_, G_, dA_ + 4, dB_, F, W_, ws, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_backward(0, 8, 8, 8, A_, B_, G_, dA_, dB_, F, W_, ws, None) == nat.QT_ERR_INVALID_ARG
+    # nothing requested: valid no-op without touching the device
+    assert nat.qt_tprod_backward(*ok, A_, B_, G_, None, None, F, W_, ws, None) == nat.QT_OK
