@@ -32,6 +32,7 @@ from .tproduct import (  # noqa: F401
     tprod,
     tprod_faces,
     tprod_rows,
+    tprod_cols,
     tprod_entries,
     tconjT,
     identity,

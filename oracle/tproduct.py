@@ -123,6 +123,15 @@ def tprod_rows(A: np.ndarray, B: np.ndarray, rows) -> np.ndarray:
     return out
 
 
+def tprod_cols(A: np.ndarray, B: np.ndarray, cols) -> np.ndarray:
+    """Selected columns j of every face of A * B: shape (4, p, m, len(cols)).
+
+    Column j of face k is sum over r of A[(k - r) mod p] . (column j of B[r]).
+    """
+    cols = np.asarray(cols, dtype=np.int64)
+    return tprod_faces(A, np.asarray(B, dtype=np.float64)[:, :, :, cols])
+
+
 def tprod_entries(A: np.ndarray, B: np.ndarray, faces, rows, cols) -> np.ndarray:
     """Single entries C[:, k, i, j] of C = A * B for index lists (k, i, j).
 
@@ -139,8 +148,9 @@ def tprod_entries(A: np.ndarray, B: np.ndarray, faces, rows, cols) -> np.ndarray
     r = np.arange(p)
     for t in range(faces.size):
         k, i, j = faces[t], rows[t], cols[t]
-        a = np.asarray(A[:, (k - r) % p][:, :, i, :], dtype=np.float64)  # (4, p, n)
-        b = np.asarray(B[:, r][:, :, :, j], dtype=np.float64)            # (4, p, n)
+        # A[:, (k - r) mod p, i, :] -> (4, p, n); B[:, r, :, j] -> (p, 4, n) -> (4, p, n)
+        a = np.asarray(A[:, (k - r) % p, i, :], dtype=np.float64)
+        b = np.moveaxis(np.asarray(B[:, r, :, j], dtype=np.float64), 0, 1)
         out[:, t] = qmul(a, b).sum(axis=(1, 2))
     return out
 

@@ -107,17 +107,13 @@ def _fd_slice_grad_B(A, B, T, rows, cols, faces, h=1e-3):
     by h * (A[(k - k0) mod p][:, l] . e_c) on every face k."""
     p = A.shape[1]
     out = np.zeros((4, len(faces), len(rows), len(cols)))
-    Rc = {}
-    for ci, j in enumerate(cols):
-        # column j of the residual: transpose trick via the entries function
-        kk, ii = np.meshgrid(np.arange(p), np.arange(A.shape[2]), indexing="ij")
-        vals = oracle.tprod_entries(A, B, kk.ravel(), ii.ravel(), np.full(kk.size, j))
-        Rc[j] = vals.reshape(4, p, A.shape[2]) - T[:, :, :, j]
+    R = oracle.tprod_cols(A, B, cols) - T[:, :, :, cols]          # (4, p, m, len(cols))
     for ri, l in enumerate(rows):
         for ci, j in enumerate(cols):
-            Rj = Rc[j]                                             # (4, p, m)
+            Rj = R[:, :, :, ci]                                    # (4, p, m)
             for fi, k0 in enumerate(faces):
-                Al = A[:, (np.arange(p) - k0) % p, :, l]            # (4, p, m)
+                # A[:, (k - k0) mod p, :, l] comes out as (p, 4, m): move to (4, p, m)
+                Al = np.moveaxis(A[:, (np.arange(p) - k0) % p, :, l], 0, 1)
                 for c in range(4):
                     e = np.zeros((4, 1, 1)); e[c] = 1.0
                     delta = qmul(Al, e)
@@ -138,9 +134,11 @@ def test_c5_full_size_fd_and_oracle():
     dA, dB = to_np(dA), to_np(dB)
     # (1) FP64 finite differences on the 16 x 4 x 10 slice of A and of B
     rows, cols, faces = list(range(16)), list(range(4)), list(range(10))
+    print("c5: FD of dA on the slice", flush=True)
     fdA = _fd_slice_grad_A(A, B, T, rows, cols, faces)
     gotA = dA[:, :10, :16, :4]
     eA = rel_err(gotA, fdA)
+    print("c5: FD of dB on the slice", flush=True)
     fdB = _fd_slice_grad_B(A, B, T, rows, cols, faces)
     gotB = dB[:, :10, :16, :4]
     eB = rel_err(gotB, fdB)

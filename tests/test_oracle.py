@@ -182,6 +182,8 @@ def test_brute_force(rng, m, n, s, p):
     np.testing.assert_allclose(ot.tprod_entries(A, B, k, i, j), ref[:, k, i, j], atol=1e-12)
     rows = np.array(sorted(set(rng.integers(0, m, 2).tolist())))
     np.testing.assert_allclose(ot.tprod_rows(A, B, rows), ref[:, :, rows, :], atol=1e-12)
+    cols = np.array(sorted(set(rng.integers(0, s, 2).tolist())))
+    np.testing.assert_allclose(ot.tprod_cols(A, B, cols), ref[:, :, :, cols], atol=1e-12)
 
 
 def test_bcirc_picture(rng):
