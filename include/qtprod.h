@@ -145,13 +145,50 @@ typedef struct {
 /* Workspace bytes for qt_tprod_batched over `count` problems (host array). */
 size_t qt_batched_workspace_size(int count, const qt_problem* probs, int precision);
 
-/* C_i = A_i * B_i for count independent problems of any sizes and p, in one
- * persistent kernel launch (plus one small descriptor upload into ws).
+/* C_i = A_i * B_i for count independent problems of any sizes and p: three
+ * persistent launches (forward tube FFT of every A_i, B_i; coupled facewise
+ * products of every frequency and output tile; inverse tube FFT of every
+ * C_i^), each walking a cost-sorted work list, after a small descriptor upload
+ * into ws (from pageable memory, so the call returns once it is staged).
  * probs is a HOST array read before the call returns.  Each problem obeys the
- * single-call preconditions.  Results equal those of qt_tprod on each problem
- * to within rounding (same arithmetic; tile order may differ). */
+ * single-call preconditions; outputs must not overlap any input or output.
+ * precision: QT_FP32 or QT_SPLIT_BF16; every p must be 7-smooth and <= 64.
+ * The first call per device and precision runs the autotuner (allocates and
+ * synchronises once).  Same arithmetic as qt_tprod per problem (tile shapes
+ * may differ, hence rounding order).  For graph replays use the plan API. */
 int qt_tprod_batched(int count, const qt_problem* probs, int precision,
                      void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Batched plan: the work lists of one batch, built once, with the three
+ * persistent launches captured into a hipGraph.  The plan refers to the
+ * problems' buffers and to `ws`, which must stay allocated (and untouched by
+ * other work while a replay runs) until qt_batched_plan_destroy. */
+typedef struct qt_batched_plan_s* qt_batched_plan;
+
+/* Build a plan for count problems (host array, read during the call): run the
+ * autotuner if it has not run for this device and precision, create missing
+ * twiddle tables, upload the work lists into ws, synchronise `stream`, and
+ * capture + instantiate the graph.  Not capture-safe itself.  precision:
+ * QT_FP32 or QT_SPLIT_BF16; every p must be 7-smooth and <= 64 (else
+ * QT_ERR_UNSUPPORTED). */
+int qt_batched_plan_create(int count, const qt_problem* probs, int precision, void* ws,
+                           size_t ws_bytes, hipStream_t stream, qt_batched_plan* plan);
+
+/* Replay the plan on `stream` (one hipGraphLaunch): recomputes every C_i from
+ * the current contents of A_i and B_i. */
+int qt_batched_plan_launch(qt_batched_plan plan, hipStream_t stream);
+
+/* Release the plan's graph (the caller's buffers are untouched). */
+int qt_batched_plan_destroy(qt_batched_plan plan);
+
+/* Run (or load from the file named by the environment variable
+ * QT_TUNE_CACHE) the autotuner for `precision` on the current device: it times
+ * every facewise tile shape on a calibration problem to fit the per-tile cost
+ * model t = alpha + beta * ceil(n / 16), and times both radix orders of the
+ * persistent FFT for every batched p.  Allocates scratch memory and
+ * synchronises `stream`.  Single-problem calls then use the cost model for
+ * their tile shape too. */
+int qt_autotune(int precision, hipStream_t stream);
 
 /* Workspace bytes needed by qt_tprod_backward. */
 size_t qt_backward_workspace_size(int m, int n, int s, int p, int precision);

@@ -47,6 +47,11 @@ SIGNATURES = {
     "qt_tprod": (_I, [_I, _I, _I, _I, _P, _P, _P, _I, _P, _SZ, _P]),
     "qt_batched_workspace_size": (_SZ, [_I, ctypes.POINTER(qt_problem), _I]),
     "qt_tprod_batched": (_I, [_I, ctypes.POINTER(qt_problem), _I, _P, _SZ, _P]),
+    "qt_batched_plan_create": (_I, [_I, ctypes.POINTER(qt_problem), _I, _P, _SZ, _P,
+                                    ctypes.POINTER(ctypes.c_void_p)]),
+    "qt_batched_plan_launch": (_I, [_P, _P]),
+    "qt_batched_plan_destroy": (_I, [_P]),
+    "qt_autotune": (_I, [_I, _P]),
     "qt_backward_workspace_size": (_SZ, [_I, _I, _I, _I, _I]),
     "qt_tprod_backward": (_I, [_I, _I, _I, _I, _P, _P, _P, _P, _P, _I, _P, _SZ, _P]),
 }
@@ -130,6 +135,25 @@ def qt_batched_workspace_size(count, probs, precision) -> int:
 
 def qt_tprod_batched(count, probs, precision, ws, ws_bytes, stream=0) -> int:
     return lib().qt_tprod_batched(count, probs, precision, ws, ws_bytes, stream)
+
+
+def qt_batched_plan_create(count, probs, precision, ws, ws_bytes, stream=0):
+    """Returns (status, plan handle as int or None)."""
+    h = ctypes.c_void_p()
+    st = lib().qt_batched_plan_create(count, probs, precision, ws, ws_bytes, stream, ctypes.byref(h))
+    return st, h.value
+
+
+def qt_batched_plan_launch(plan, stream=0) -> int:
+    return lib().qt_batched_plan_launch(plan, stream)
+
+
+def qt_batched_plan_destroy(plan) -> int:
+    return lib().qt_batched_plan_destroy(plan)
+
+
+def qt_autotune(precision, stream=0) -> int:
+    return lib().qt_autotune(precision, stream)
 
 
 def qt_backward_workspace_size(m, n, s, p, precision) -> int:

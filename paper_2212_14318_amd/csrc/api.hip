@@ -49,6 +49,7 @@ size_t fourier_bytes(long rows, long cols, long p, int prec) {
 
 bool p_supported(int p, int prec) {
     if (p < 1 || p > QT_MAX_P) return false;
+    if (prec == QT_SPLIT_FP16) return false;   // not served by this build
     return prec == QT_FP64 ? qt::tube_fft_supported<double>(p) : qt::tube_fft_supported<float>(p);
 }
 
@@ -64,7 +65,10 @@ struct PlanKeyHash {
 std::mutex g_plan_mutex;
 std::unordered_map<PlanKey, Twiddles, PlanKeyHash> g_plans;
 
-int get_plan(int p, hipStream_t stream, Twiddles* out) {
+}  // namespace
+
+namespace qt {
+int get_twiddles(int p, hipStream_t stream, Twiddles* out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return QT_ERR_HIP;
     std::lock_guard<std::mutex> lock(g_plan_mutex);
@@ -88,12 +92,17 @@ int get_plan(int p, hipStream_t stream, Twiddles* out) {
     *out = tw;
     return QT_OK;
 }
+}  // namespace qt
+
+namespace {
+using qt::get_twiddles;
+int get_plan(int p, hipStream_t stream, Twiddles* out) { return get_twiddles(p, stream, out); }
 
 // ------------------------------------------------------------- forward path
 template <typename T>
 hipError_t facewise(const FacewiseArgs<T>& fa, int prec, hipStream_t stream) {
     if constexpr (sizeof(T) == 8) return qt::launch_facewise_f64(fa, stream);
-    else return qt::launch_facewise_f32(fa, prec, stream);
+    else return qt::launch_facewise_f32(fa, prec, stream, qt::choose_tile(fa.m, fa.n, fa.s, prec));
 }
 
 int hip_status(hipError_t e) {
@@ -308,17 +317,6 @@ int qt_tprod(int m, int n, int s, int p, const void* A, const void* B, void* C, 
                                  (char*)ws, stream);
     return run_tprod<float>(m, n, s, p, (const float*)A, (const float*)B, (float*)C, precision,
                             (char*)ws, stream);
-}
-
-size_t qt_batched_workspace_size(int count, const qt_problem* probs, int precision) {
-    (void)count; (void)probs; (void)precision;
-    return 0;
-}
-
-int qt_tprod_batched(int count, const qt_problem* probs, int precision, void* ws, size_t ws_bytes,
-                     hipStream_t stream) {
-    (void)count; (void)probs; (void)precision; (void)ws; (void)ws_bytes; (void)stream;
-    return QT_ERR_UNSUPPORTED;
 }
 
 size_t qt_backward_workspace_size(int m, int n, int s, int p, int precision) {

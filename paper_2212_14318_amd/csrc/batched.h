@@ -1,0 +1,54 @@
+// Descriptors and launchers of the batched (many problems, one launch per
+// phase) T-product.
+#pragma once
+#include "qt_internal.h"
+
+namespace qt {
+
+// One tube-FFT job of the batch (one quaternion tensor), FP32.
+struct BatchFftJob {
+    const float* src;
+    float* dst;
+    const float2* tw;          // twiddle table of p
+    int rows, cols, src_ld, dst_ld;
+    int p, pol;                // length and radix-order policy (0 or 1)
+};
+
+// 256 consecutive positions of one CD part of one job.
+struct BatchFftItem {
+    int job, part, e0, pad;
+};
+
+// One problem of the facewise phase and its tile shape (detail::TileCfg).
+struct BatchGemmProb {
+    FacewiseArgs<float> a;
+    int cfg, pad0, pad1, pad2;
+};
+
+// One output tile (tm, tn) at frequency f of problem prob.
+struct BatchGemmItem {
+    int prob, f, tm, tn;
+};
+
+// True if the persistent FFT kernel has a case for p (7-smooth, p <= 64).
+bool batched_fft_supported(int p);
+
+// Persistent tube FFT over a heterogeneous item list (grid blocks stride the
+// list).  Descriptor arrays are device pointers.
+hipError_t launch_batched_fft(bool inverse, const BatchFftJob* jobs, const BatchFftItem* items,
+                              int nitems, int grid, hipStream_t stream);
+
+// Persistent coupled facewise products over a heterogeneous tile list.
+// precision: 0 = FP32, 1 = split bf16.
+hipError_t launch_batched_gemm(int precision, const BatchGemmProb* probs, const BatchGemmItem* items,
+                               int nitems, int grid, hipStream_t stream);
+
+// Dynamic LDS bytes of the persistent facewise kernel for a precision.
+size_t batched_gemm_smem_bytes(int precision);
+
+// Resident workgroups per CU of the persistent kernels (occupancy API).
+int batched_gemm_blocks_per_cu(int precision);
+int batched_fft_fwd_blocks_per_cu();
+int batched_fft_inv_blocks_per_cu();
+
+}  // namespace qt

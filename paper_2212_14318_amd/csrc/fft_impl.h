@@ -46,9 +46,20 @@ __device__ __forceinline__ V twiddle(int e, const V* __restrict__ tw) {
     return w;
 }
 
+// Radix order of the decimation (the "radix plan"):
+//   POL = 0: powers of two first (4, then 2), then 3, 5, 7;
+//   POL = 1: odd primes first (7, 5, 3), then 4, 2.
+// Both give the same transform; they differ in the number and position of
+// twiddle multiplications.  The batched path lets its autotuner pick one per p.
+template <int POL>
 constexpr int pick_radix(int n) {
-    return (n % 4 == 0) ? 4 : (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : (n % 5 == 0) ? 5
-         : (n % 7 == 0) ? 7 : n;
+    if constexpr (POL == 0) {
+        return (n % 4 == 0) ? 4 : (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : (n % 5 == 0) ? 5
+             : (n % 7 == 0) ? 7 : n;
+    } else {
+        return (n % 7 == 0) ? 7 : (n % 5 == 0) ? 5 : (n % 3 == 0) ? 3 : (n % 4 == 0) ? 4
+             : (n % 2 == 0) ? 2 : n;
+    }
 }
 
 // In-register DFT of length R (the butterfly of one radix stage).
@@ -97,10 +108,10 @@ __device__ __forceinline__ void small_dft(V (&t)[R], const V* __restrict__ tw) {
 
 // Decimation in time: N = R M.  Sub-transforms of the R decimated sequences
 // x[j R + r], then X[q + M u] = sum_r w_R^(r u) (w_N^(r q) Y_r[q]).
-template <int P, int N, bool INV, typename V>
+template <int P, int N, bool INV, typename V, int POL = 0>
 struct Dft {
     static __device__ __forceinline__ void run(V (&x)[N], const V* __restrict__ tw) {
-        constexpr int R = pick_radix(N);
+        constexpr int R = pick_radix<POL>(N);
         constexpr int M = N / R;
         if constexpr (M == 1) {
             small_dft<P, R, INV>(x, tw);
@@ -111,7 +122,7 @@ struct Dft {
 #pragma unroll
                 for (int j = 0; j < M; ++j) sub[r][j] = x[j * R + r];
 #pragma unroll
-            for (int r = 0; r < R; ++r) Dft<P, M, INV, V>::run(sub[r], tw);
+            for (int r = 0; r < R; ++r) Dft<P, M, INV, V, POL>::run(sub[r], tw);
 #pragma unroll
             for (int q = 0; q < M; ++q) {
                 V t[R];
@@ -131,17 +142,12 @@ struct FftJobs2 {
     FftJob<T> j[2];
 };
 
-// grid: x covers rows*cols of the largest job, y = 2 * njobs (job, CD part).
-template <int P, bool INV, typename T>
-__global__ void __launch_bounds__(256)
-tube_fft_kernel(FftJobs2<T> jobs, const typename Vec2<T>::type* __restrict__ tw) {
+// Transform one complex tube: part 0 = X1 (planes 0, 1), part 1 = X2
+// (planes 2, 3) at flattened position e = i * cols + c of job jb.
+template <int P, bool INV, typename T, int POL = 0>
+__device__ __forceinline__ void tube_fft_one(const FftJob<T>& jb, int part, long e,
+                                             const typename Vec2<T>::type* __restrict__ tw) {
     using V = typename Vec2<T>::type;
-    const int job = blockIdx.y >> 1;
-    const int part = blockIdx.y & 1;                 // 0: X1 (planes 0,1), 1: X2 (planes 2,3)
-    const FftJob<T> jb = jobs.j[job];
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long count = (long)jb.rows * jb.cols;
-    if (e >= count) return;
     const int i = (int)(e / jb.cols);
     const int c = (int)(e - (long)i * jb.cols);
     const size_t sface = (size_t)jb.rows * jb.src_ld;
@@ -154,13 +160,25 @@ tube_fft_kernel(FftJobs2<T> jobs, const typename Vec2<T>::type* __restrict__ tw)
     V x[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) x[k] = V{sre[k * sface], sim[k * sface]};
-    Dft<P, P, INV, V>::run(x, tw);
+    Dft<P, P, INV, V, POL>::run(x, tw);
     const T scale = INV ? T(1) / T(P) : T(1);
 #pragma unroll
     for (int k = 0; k < P; ++k) {
         dre[k * dface] = x[k].x * scale;
         dim[k * dface] = x[k].y * scale;
     }
+}
+
+// grid: x covers rows*cols of the largest job, y = 2 * njobs (job, CD part).
+template <int P, bool INV, typename T>
+__global__ void __launch_bounds__(256)
+tube_fft_kernel(FftJobs2<T> jobs, const typename Vec2<T>::type* __restrict__ tw) {
+    const int job = blockIdx.y >> 1;
+    const int part = blockIdx.y & 1;                 // 0: X1 (planes 0,1), 1: X2 (planes 2,3)
+    const FftJob<T> jb = jobs.j[job];
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)jb.rows * jb.cols) return;
+    tube_fft_one<P, INV, T>(jb, part, e, tw);
 }
 
 template <int P, bool INV, typename T>

@@ -59,8 +59,11 @@ struct FacewiseArgs {
 };
 
 // C^[f] = A^[f] B^[f] coupled with -f (see qtprod.h) for every f.
-// precision: 0 = FP32 MFMA, 1 = split bf16, 2 = split fp16 (float only).
-hipError_t launch_facewise_f32(const FacewiseArgs<float>& a, int precision, hipStream_t stream);
+// precision: 0 = FP32 MFMA, 1 = split bf16, 2 = split fp16 (float only; needs
+// `scales`: 2p power-of-two scales, [f] for A^ and [p + f] for B^).
+// tile_cfg: detail::TileCfg (0 = 128x64, 1 = 64x128, 2 = 64x64).
+hipError_t launch_facewise_f32(const FacewiseArgs<float>& a, int precision, hipStream_t stream,
+                               int tile_cfg = 0, const float* scales = nullptr);
 hipError_t launch_facewise_f64(const FacewiseArgs<double>& a, hipStream_t stream);
 
 // Tensor conjugate transpose job: src is rows x cols x p ([4][p][rows][cols]),
@@ -76,5 +79,13 @@ struct ConjTJob {
 // dst = src^H for one or two jobs in one launch.
 template <typename T>
 hipError_t launch_conj_transpose(const ConjTJob<T>* jobs, int njobs, hipStream_t stream);
+
+// Twiddle table of p on the current device from the plan cache (created on
+// first use on `stream`, which is then synchronised once).  Returns a qt_status.
+int get_twiddles(int p, hipStream_t stream, Twiddles* out);
+
+// Tile shape (detail::TileCfg) for one facewise product: from the autotuner's
+// cost model when it has run on this device for this precision, else 128x64.
+int choose_tile(int m, int n, int s, int precision);
 
 }  // namespace qt

@@ -159,6 +159,58 @@ def tprod_batched(As, Bs, precision="fp32", outs=None):
     return outs
 
 
+class BatchedPlan:
+    """A captured batch: C_i = A_i * B_i for fixed tensors, replayed with one
+    hipGraphLaunch per call.  Keeps the tensors and the workspace alive."""
+
+    def __init__(self, As, Bs, precision="fp32", outs=None):
+        prec = _prec(precision)
+        if len(As) != len(Bs) or not As:
+            raise ValueError("need equally many A and B tensors (at least one)")
+        if outs is None:
+            outs = [torch.empty((4, A.shape[1], A.shape[2], B.shape[3]), dtype=A.dtype,
+                                device=A.device) for A, B in zip(As, Bs)]
+        items = []
+        for A, B, C in zip(As, Bs, outs):
+            _check_tensor(A, "A", prec)
+            _check_tensor(B, "B", prec)
+            _check_tensor(C, "C", prec)
+            items.append((A.shape[2], A.shape[3], B.shape[3], A.shape[1], A.data_ptr(),
+                          B.data_ptr(), C.data_ptr()))
+        self._keep = (list(As), list(Bs))
+        self.outs = outs
+        probs = nat.make_problems(items)
+        need = nat.qt_batched_workspace_size(len(items), probs, prec)
+        self.ws = workspace(need, As[0].device)
+        self.device = As[0].device
+        st, self.handle = nat.qt_batched_plan_create(len(items), probs, prec, self.ws.data_ptr(),
+                                                     self.ws.numel(), _stream(self.device))
+        nat.check(st, "qt_batched_plan_create")
+
+    def launch(self):
+        nat.check(nat.qt_batched_plan_launch(self.handle, _stream(self.device)),
+                  "qt_batched_plan_launch")
+        return self.outs
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.current_stream(self.device).synchronize()
+            nat.check(nat.qt_batched_plan_destroy(self.handle), "qt_batched_plan_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(precision="fp32", device=None):
+    """Run the device autotuner (tile cost model, FFT radix orders) now."""
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    nat.check(nat.qt_autotune(_prec(precision), _stream(dev)), "qt_autotune")
+
+
 class QTProd(torch.autograd.Function):
     """C = A * B with the hand-written Fourier-domain backward.
 

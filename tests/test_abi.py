@@ -163,3 +163,39 @@ def test_backward_rejects_bad_args():
     assert nat.qt_tprod_backward(0, 8, 8, 8, A_, B_, G_, dA_, dB_, F, W_, ws, None) == nat.QT_ERR_INVALID_ARG
     # nothing requested: valid no-op without touching the device
     assert nat.qt_tprod_backward(*ok, A_, B_, G_, None, None, F, W_, ws, None) == nat.QT_OK
+
+
+def test_batched_rejects_bad_args():
+    F = nat.QT_FP32
+    good = [(8, 8, 8, 8, A_, B_, C_)]
+    probs = nat.make_problems(good)
+    ws = nat.qt_batched_workspace_size(1, probs, F)
+    assert ws > 0
+    assert nat.qt_tprod_batched(0, probs, F, W_, ws, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_batched(1, probs, F, W_, ws - 1, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_batched(1, probs, F, None, ws, None) == nat.QT_ERR_INVALID_ARG
+    bad = nat.make_problems([(0, 8, 8, 8, A_, B_, C_)])
+    assert nat.qt_tprod_batched(1, bad, F, W_, 1 << 30, None) == nat.QT_ERR_INVALID_ARG
+    alias = nat.make_problems([(8, 8, 8, 8, A_, B_, A_)])
+    assert nat.qt_tprod_batched(1, alias, F, W_, 1 << 30, None) == nat.QT_ERR_INVALID_ARG
+    # two problems writing overlapping outputs; an output overlapping another's input
+    two = nat.make_problems([(8, 8, 8, 8, A_, B_, C_), (8, 8, 8, 8, A_, B_, C_ + 1024)])
+    assert nat.qt_tprod_batched(2, two, F, W_, 1 << 30, None) == nat.QT_ERR_INVALID_ARG
+    cross = nat.make_problems([(8, 8, 8, 8, A_, B_, C_), (8, 8, 8, 8, C_, B_, C_ + (1 << 20))])
+    assert nat.qt_tprod_batched(2, cross, F, W_, 1 << 30, None) == nat.QT_ERR_INVALID_ARG
+    # shared inputs are fine; unsupported p or precision is reported as such
+    prime = nat.make_problems([(8, 8, 8, 11, A_, B_, C_)])
+    assert nat.qt_tprod_batched(1, prime, F, W_, 1 << 30, None) == nat.QT_ERR_UNSUPPORTED
+    assert nat.qt_tprod_batched(1, probs, nat.QT_FP64, W_, 1 << 30, None) == nat.QT_ERR_UNSUPPORTED
+    st, plan = nat.qt_batched_plan_create(0, probs, F, W_, ws, None)
+    assert st == nat.QT_ERR_INVALID_ARG and plan is None
+    assert nat.qt_batched_plan_launch(None, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_batched_plan_destroy(None) == nat.QT_ERR_INVALID_ARG
+
+
+def test_batched_workspace_size_grows():
+    F = nat.QT_FP32
+    one = nat.make_problems([(16, 16, 16, 8, A_, B_, C_)])
+    two = nat.make_problems([(16, 16, 16, 8, A_, B_, C_), (200, 30, 70, 45, A_, B_, C_)])
+    assert 0 < nat.qt_batched_workspace_size(1, one, F) < nat.qt_batched_workspace_size(2, two, F)
+    assert nat.qt_batched_workspace_size(0, one, F) == 0

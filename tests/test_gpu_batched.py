@@ -1,0 +1,107 @@
+"""GPU parity of the batched path (qt_tprod_batched, qt_batched_plan_*)
+against the FP64 oracle and against single-problem calls."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_2212_14318_amd import BatchedPlan, autotune, tprod, tprod_batched
+
+from gpu_util import rel_err, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOLS = {"fp32": 1e-5, "split_bf16": 5e-5}
+P_SET = [1, 2, 3, 5, 7, 8, 12, 16, 30, 32, 45, 64]
+
+
+def small_batch(count, seed, lo=1, hi=150):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(count):
+        m, n, s = (int(x) for x in rng.integers(lo, hi + 1, 3))
+        p = int(rng.choice(P_SET))
+        out.append((synth.quat_tensor(m, n, p, seed=seed * 1000 + 2 * i),
+                    synth.quat_tensor(n, s, p, seed=seed * 1000 + 2 * i + 1)))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_autotune_runs(prec):
+    autotune(prec)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_batched_matches_oracle(prec):
+    batch = small_batch(24, seed=11)
+    As = [to_dev(A) for A, _ in batch]
+    Bs = [to_dev(B) for _, B in batch]
+    Cs = tprod_batched(As, Bs, prec)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for (A, B), C in zip(batch, Cs):
+        e = rel_err(to_np(C), oracle.tprod_faces(A, B))
+        worst = max(worst, e)
+    print(f"{prec} batched worst rel err over 24 problems: {worst:.3e}")
+    assert worst <= TOLS[prec]
+
+
+def test_batched_matches_single_calls():
+    batch = small_batch(10, seed=12, lo=20, hi=200)
+    As = [to_dev(A) for A, _ in batch]
+    Bs = [to_dev(B) for _, B in batch]
+    Cs = tprod_batched(As, Bs, "fp32")
+    for A, B, C in zip(As, Bs, Cs):
+        ref = tprod(A, B, "fp32")
+        assert rel_err(to_np(C), to_np(ref)) <= 2e-6
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_plan_replays_track_inputs(prec):
+    """Replay the captured graph several times with eager work and syncs in
+    between; every replay must equal the eager single-call results."""
+    batch = small_batch(12, seed=13, lo=8, hi=120)
+    As = [to_dev(A) for A, _ in batch]
+    Bs = [to_dev(B) for _, B in batch]
+    plan = BatchedPlan(As, Bs, prec)
+    try:
+        for r in range(3):
+            for A in As:                       # eager work between replays
+                A.mul_(-1.5 if r % 2 else 0.5)
+            torch.cuda.synchronize()
+            outs = plan.launch()
+            torch.cuda.synchronize()
+            for A, B, C in zip(As, Bs, outs):
+                ref = tprod(A, B, prec)
+                torch.cuda.synchronize()
+                assert rel_err(to_np(C), to_np(ref)) <= 2e-6
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_c4_full_batch(prec):
+    sizes = synth.batch_problem_sizes()
+    As, Bs = [], []
+    for i, (m, n, s, p) in enumerate(sizes):
+        A, B = synth.batch_problem_inputs(i, int(m), int(n), int(s), int(p))
+        As.append(to_dev(A))
+        Bs.append(to_dev(B))
+    print(f"c4: {len(sizes)} problems on the device", flush=True)
+    Cs = tprod_batched(As, Bs, prec)
+    torch.cuda.synchronize()
+    rng = np.random.Generator(np.random.PCG64(4200))
+    num = den = 0.0
+    worst = 0.0
+    for i, (m, n, s, p) in enumerate(sizes):
+        A, B = synth.batch_problem_inputs(i, int(m), int(n), int(s), int(p))
+        k = rng.integers(0, p, 6); r = rng.integers(0, m, 6); c = rng.integers(0, s, 6)
+        ref = oracle.tprod_entries(A, B, k, r, c)
+        got = to_np(Cs[i][:, k, r, c])
+        d = float(np.sum((got - ref) ** 2)); e = float(np.sum(ref ** 2))
+        num += d; den += e
+        worst = max(worst, np.sqrt(d / e))
+    err = np.sqrt(num / den)
+    print(f"c4 {prec}: sampled rel err {err:.3e}, worst problem {worst:.3e}")
+    assert err <= TOLS[prec] and worst <= 4 * TOLS[prec]
