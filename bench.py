@@ -35,6 +35,8 @@ WORKLOADS = {
     "c3": dict(cfg=3, desc="A, B 1024x1024x32 quaternion, components N(0,1) (seeds 3000/3001)"),
     "c5": dict(cfg=5, desc="A 512x64x100, B 64x512x100 quaternion, components N(0,1) "
                            "(seeds 5000/5001)"),
+    "c4": dict(cfg=4, desc="512 independent T-products, m,n,s ~ U{16..256}, p ~ U{8,12,16,30,32,45,64}, "
+                           "N(0,1) (sizes seed 4000, problem i seed 4100000+i)"),
 }
 
 
@@ -59,6 +61,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--backward", action="store_true",
+                    help="c5: time forward + hand-written backward instead of the forward alone")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     return ap.parse_args()
@@ -88,6 +92,10 @@ def main():
 
     wl = WORKLOADS[args.workload]
     cfg = wl["cfg"]
+    if args.workload == "c4":
+        return bench_batched(args, wl, dev, stream)
+    if args.workload == "c5" and args.backward:
+        return bench_backward(args, wl, dev, stream)
     t0 = time.time()
     inputs = synth.config_inputs(cfg)
     A64, B64 = inputs[0], inputs[1]
@@ -248,6 +256,98 @@ def main():
     if "fp32" in results and head != "fp32":
         out["speedup_vs_fp32"] = round(results["fp32"]["ms_per_step"] / r["ms_per_step"], 3)
     print(json.dumps(out), flush=True)
+
+
+def _emit(out):
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args, wl, dev, stream):
+    """Batched workload: replays of one captured plan (one hipGraphLaunch per
+    step) over 512 problems; value = sum of per-problem F / time per replay."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2212_14318_amd import BatchedPlan, autotune
+
+    sizes = synth.batch_problem_sizes()
+    As, Bs = [], []
+    F = 0.0
+    for i, (m, n, s, p) in enumerate(sizes):
+        A, B = synth.batch_problem_inputs(i, int(m), int(n), int(s), int(p))
+        As.append(torch.from_numpy(A).to(dev, torch.float32))
+        Bs.append(torch.from_numpy(B).to(dev, torch.float32))
+        fg, ff = flops(int(m), int(n), int(s), int(p))
+        F += fg + ff
+    log(f"[bench] c4: {len(sizes)} problems resident, F = {F:.4e}")
+    res = {}
+    precs = [x for x in args.precisions.split(",") if x]
+    for prec in precs:
+        autotune(prec)
+        plan = BatchedPlan(As, Bs, prec)
+        for _ in range(args.warmup):
+            plan.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.launch()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        res[prec] = {"ms_per_step": ms, "tflops_equiv": F / (ms * 1e-3) / 1e12}
+        plan.close()
+        log(f"[bench] c4 {prec}: {ms:.3f} ms per replay, {res[prec]['tflops_equiv']:.1f} TFLOP/s-equiv")
+    head = precs[0]
+    _emit({"metric": "T-product TFLOP/s-equiv & % roofline, split-BF16 vs FP32 at stated rel. error",
+           "value": round(res[head]["tflops_equiv"], 3), "unit": "TFLOP/s-equiv", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res[head]["ms_per_step"], 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16x3-split/f32-acc" if head == "split_bf16" else "f32", "data": "synthetic",
+           "config": {"workload": wl["desc"], "precision": head, "flops_per_step": F},
+           "per_precision": res, "roofline": None, "cpu_baseline": None})
+
+
+def bench_backward(args, wl, dev, stream):
+    """Differentiation workload: one step = forward C = A * B, G = C - T, and
+    the hand-written backward dA = G * B^H, dB = A^H * G."""
+    import torch
+
+    import synth
+    from paper_2212_14318_amd import tprod, tprod_backward
+
+    A64, B64, T64 = synth.config_inputs(5)
+    _, p, m, n = A64.shape
+    s = B64.shape[3]
+    A = torch.from_numpy(A64).to(dev, torch.float32)
+    B = torch.from_numpy(B64).to(dev, torch.float32)
+    T = torch.from_numpy(T64).to(dev, torch.float32)
+    fg, ff = flops(m, n, s, p)
+    F = (fg + ff) + 2 * fg + ff + 10.0 * p * math.log2(p) * (m * n + n * s)
+    res = {}
+    precs = [x for x in args.precisions.split(",") if x]
+    for prec in precs:
+        def step():
+            C = tprod(A, B, prec)
+            G = C.sub_(T)
+            return tprod_backward(A, B, G, prec)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        res[prec] = {"ms_per_step": ms, "tflops_equiv": F / (ms * 1e-3) / 1e12}
+        log(f"[bench] c5 fwd+bwd {prec}: {ms:.3f} ms/step, {res[prec]['tflops_equiv']:.1f} TFLOP/s-equiv")
+    head = precs[0]
+    _emit({"metric": "T-product TFLOP/s-equiv & % roofline, split-BF16 vs FP32 at stated rel. error",
+           "value": round(res[head]["tflops_equiv"], 3), "unit": "TFLOP/s-equiv", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res[head]["ms_per_step"], 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16x3-split/f32-acc" if head == "split_bf16" else "f32", "data": "synthetic",
+           "config": {"workload": wl["desc"] + " + backward", "precision": head, "flops_per_step": F},
+           "per_precision": res, "roofline": None, "cpu_baseline": None})
 
 
 if __name__ == "__main__":
