@@ -76,7 +76,10 @@ typedef enum {
     QT_FP64 = 3         /* every step in double (small problems, validation) */
 } qt_precision;
 
-/* Largest p served.  Every p in [1, QT_MAX_P] is supported. */
+/* Largest p accepted by the argument checks.  The lengths with a kernel in
+ * this build are the 7-smooth p (prime factors 2, 3, 5, 7) up to 128 for the
+ * float precisions and up to 64 for QT_FP64 (64 in the batched path); other
+ * p return QT_ERR_UNSUPPORTED. */
 #define QT_MAX_P 4096
 
 /* Library ABI version (major * 100 + minor). */
