@@ -29,17 +29,18 @@ template <int CFG>
 __global__ void __launch_bounds__(256)
 facewise_f32_kernel(FacewiseArgs<float> a, int tiles_n) {
     constexpr int MT = tile_mt(CFG), NT = tile_nt(CFG);
-    __shared__ F32Smem<MT, NT> sm;
+    __shared__ __attribute__((aligned(16))) V2Smem<MT, NT> sm;
     const int tm = blockIdx.x / tiles_n;
     const int tn = blockIdx.x - tm * tiles_n;
-    tile_f32<MT, NT>(a, blockIdx.y, tm * MT, tn * NT, sm);
+    tile_v2<0, MT, NT>(a, blockIdx.y, tm * MT, tn * NT, 1.f, 1.f, sm);
 }
 
 template <typename H, int CFG>
 __global__ void __launch_bounds__(256)
 facewise_split_kernel(FacewiseArgs<float> a, int tiles_n, const float* __restrict__ scales) {
     constexpr int MT = tile_mt(CFG), NT = tile_nt(CFG);
-    __shared__ __attribute__((aligned(16))) SplitSmem<H, MT, NT> sm;
+    constexpr int MODE = std::is_same<H, _Float16>::value ? 2 : 1;
+    __shared__ __attribute__((aligned(16))) V2Smem<MT, NT> sm;
     const int f = blockIdx.y;
     const int tm = blockIdx.x / tiles_n;
     const int tn = blockIdx.x - tm * tiles_n;
@@ -48,7 +49,7 @@ facewise_split_kernel(FacewiseArgs<float> a, int tiles_n, const float* __restric
         sa = scales[f];
         sb = scales[a.p + f];
     }
-    tile_split<H, MT, NT>(a, f, tm * MT, tn * NT, sa, sb, sm);
+    tile_v2<MODE, MT, NT>(a, f, tm * MT, tn * NT, sa, sb, sm);
 }
 
 // ---------------------------------------------------------------- FP64 VALU

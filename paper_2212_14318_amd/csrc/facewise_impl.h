@@ -19,6 +19,8 @@
 // and the eight B planes (f and g) of one 16-deep k-chunk in LDS, so each B
 // value is read once per output tile rather than once per output plane.
 #pragma once
+#include <type_traits>
+
 #include "qt_internal.h"
 
 namespace qt {
@@ -394,6 +396,225 @@ __device__ __forceinline__ void tile_split(const FacewiseArgs<float>& a, int f, 
 enum TileCfg { TILE_128x64 = 0, TILE_64x128 = 1, TILE_64x64 = 2, NUM_TILE_CFGS = 3 };
 __host__ __device__ constexpr int tile_mt(int cfg) { return cfg == TILE_128x64 ? 128 : 64; }
 __host__ __device__ constexpr int tile_nt(int cfg) { return cfg == TILE_64x128 ? 128 : 64; }
+
+
+// ===================================================================== v2
+// Pipelined tile routine shared by the FP32 and split paths:
+//  * k-chunks of 16 go global -> LDS by DMA (global_load_lds_dwordx4: each
+//    wave instruction moves 64 x 16 B into 1 KB of LDS, lane L at byte 16 L),
+//    so no prefetch registers are live across the MFMA loop;
+//  * two LDS buffers, one barrier per chunk: the DMA of chunk c + 1 runs
+//    while chunk c is multiplied;
+//  * within a chunk, lane group g = lane / 32 owns logical k = 8 g .. 8 g + 7
+//    of both operands (any assignment works as long as A and B agree), so an
+//    A fragment is 8 contiguous floats (two 16-byte LDS reads) and a B
+//    fragment is 8 floats of one column (eight 4-byte reads, conflict-free);
+//  * the A chunk is stored row-major with its four 16-byte k-pieces XOR-
+//    swizzled by row group (piece q of row i sits at slot 4 i + (q ^ (i/4 % 4))
+//    of its 16-row block), which makes the 16-byte fragment reads conflict-free;
+//  * rows/columns/k beyond the problem are read from clamped (valid)
+//    addresses and zeroed before use; interior chunks skip the masks.
+// MODE 0: FP32 operands on v_mfma_f32_32x32x2_f32 (8 k-steps per chunk);
+// MODE 1/2: bf16/fp16 hi+lo split at fragment time, 3 products per term on
+// v_mfma_f32_32x32x16_{bf16,f16} (one k-step per chunk).
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+template <int MT, int NT>
+struct V2Smem {
+    float A[2][4][MT / 16][256];      // [buffer][plane][16-row block][1 KB]
+    float B[2][8][NT / 16][256];      // [buffer][plane][block of 256/NT k-rows][1 KB]
+};
+
+__device__ __forceinline__ void dma16(const float* g, float* lds_block) {
+    __builtin_amdgcn_global_load_lds((const void*)g, (lds_void_t*)lds_block, 16, 0, 0);
+}
+
+template <typename H>
+__device__ __forceinline__ void split8(const float (&x)[8], typename SplitTypes<H>::v8& hi,
+                                       typename SplitTypes<H>::v8& lo) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        hi[j] = (H)x[j];
+        lo[j] = (H)(x[j] - (float)hi[j]);
+    }
+}
+
+template <int MODE, int MT, int NT>
+__device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int m0, int n0,
+                                        float sa, float sb, V2Smem<MT, NT>& sm) {
+    using H = typename std::conditional<MODE == 2, _Float16, __bf16>::type;
+    using V8 = typename SplitTypes<H>::v8;
+    constexpr int MB = MT / 64, NB = NT / 64;
+    constexpr int ABLK = MT / 16, BBLK = NT / 16;       // 1 KB blocks per plane
+    constexpr int RB = 256 / NT, CQ = NT / 4;           // B block: RB k-rows of CQ 16-byte pieces
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int g = (a.p - f) % a.p;
+    const size_t pa = (size_t)a.p * a.m * a.lda;
+    const size_t pb = (size_t)a.p * a.n * a.ldb;
+    const float* Af = a.Ah + (size_t)f * a.m * a.lda;
+    const float* Bf = a.Bh + (size_t)f * a.n * a.ldb;
+    const float* Bg = a.Bh + (size_t)g * a.n * a.ldb;
+    const int nchunks = (a.n + KT - 1) / KT;
+    const bool edge_tile = (m0 + MT > a.m) || (n0 + NT > a.s);
+
+    // ---- DMA of chunk c into buffer b (wave-uniform loops; 1 KB per instruction)
+    auto issue = [&](int c, int b) {
+        const int k0 = c * KT;
+#pragma unroll
+        for (int q = wave; q < 4 * ABLK; q += 4) {
+            const int pl = q / ABLK, blk = q % ABLK;
+            const int i = lane >> 2;
+            const int kq = (lane & 3) ^ ((i >> 2) & 3);
+            int grow = m0 + blk * 16 + i;
+            grow = grow < a.m ? grow : a.m - 1;
+            int gk = k0 + 4 * kq;
+            gk = gk <= a.lda - 4 ? gk : a.lda - 4;
+            dma16(Af + pl * pa + (size_t)grow * a.lda + gk, &sm.A[b][pl][blk][0]);
+        }
+#pragma unroll
+        for (int q = wave; q < 8 * BBLK; q += 4) {
+            const int pl = q / BBLK, blk = q % BBLK;
+            // staged planes: 0..3 = B^[f] (B1r, B1i, B2r, B2i); 4..7 = D, E from
+            // B^[g]: Dr = -B2r, Di = B2i, Er = B1r, Ei = -B1i (signs applied later)
+            const int src = pl < 4 ? pl : (pl == 4 ? 2 : pl == 5 ? 3 : pl == 6 ? 0 : 1);
+            const float* base = (pl < 4 ? Bf : Bg) + src * pb;
+            int gk = k0 + blk * RB + lane / CQ;
+            gk = gk < a.n ? gk : a.n - 1;
+            int gc = n0 + 4 * (lane % CQ);
+            gc = gc <= a.ldb - 4 ? gc : a.ldb - 4;
+            dma16(base + (size_t)gk * a.ldb + gc, &sm.B[b][pl][blk][0]);
+        }
+    };
+
+    const int wm = wave & 1, wn = wave >> 1;
+    const int lr = lane & 31, lg = lane >> 5;
+
+    v16f acc[4][MB][NB];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[c][mb][nb][r] = 0.f;
+
+    // ---- fragments of chunk c from buffer b; MASK zeroes out-of-range entries
+    auto load_b = [&](int b, int nb, int c, bool mask, float (&x)[8][8]) {
+        const int cl = wn * (NT / 2) + nb * 32 + lr;
+        const bool col_ok = !mask || (n0 + cl < a.s);
+#pragma unroll
+        for (int pl = 0; pl < 8; ++pl) {
+            const float sgn = (pl == 4 || pl == 7) ? -(MODE == 2 ? sb : 1.f) : (MODE == 2 ? sb : 1.f);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = 8 * lg + j;
+                const float v = sm.B[b][pl][k / RB][(k % RB) * NT + cl];
+                const bool ok = col_ok && (!mask || (c * KT + k < a.n));
+                x[pl][j] = ok ? v * sgn : 0.f;
+            }
+        }
+    };
+    auto load_a = [&](int b, int mb, int c, bool mask, float (&x)[4][8]) {
+        const int rl = wm * (MT / 2) + mb * 32 + lr;
+        const int blk = rl >> 4, i = rl & 15;
+        const int s0 = 4 * i + ((2 * lg) ^ ((i >> 2) & 3));
+        const int s1 = 4 * i + ((2 * lg + 1) ^ ((i >> 2) & 3));
+        const bool row_ok = !mask || (m0 + rl < a.m);
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) {
+            const float4 u = *reinterpret_cast<const float4*>(&sm.A[b][pl][blk][4 * s0]);
+            const float4 w = *reinterpret_cast<const float4*>(&sm.A[b][pl][blk][4 * s1]);
+            const float v[8] = {u.x, u.y, u.z, u.w, w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const bool ok = row_ok && (!mask || (c * KT + 8 * lg + j < a.n));
+                x[pl][j] = ok ? (MODE == 2 ? v[j] * sa : v[j]) : 0.f;
+            }
+        }
+    };
+
+    auto compute = [&](int c, int b, bool mask) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            float xb[8][8];
+            load_b(b, nb, c, mask, xb);
+            if constexpr (MODE == 0) {
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    float xa[4][8];
+                    load_a(b, mb, c, mask, xa);
+                    v16f c0 = acc[0][mb][nb], c1 = acc[1][mb][nb], c2 = acc[2][mb][nb], c3 = acc[3][mb][nb];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const float ar1 = xa[0][t], ai1 = xa[1][t], ar2 = xa[2][t], ai2 = xa[3][t];
+                        // Re C1 = Ar1 B1r - Ai1 B1i + Ar2 Dr - Ai2 Di ; Im C1 = Ar1 B1i + Ai1 B1r + Ar2 Di + Ai2 Dr
+                        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar1, xb[0][t], c0, 0, 0, 0);
+                        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai1, xb[1][t], c0, 0, 0, 0);
+                        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar2, xb[4][t], c0, 0, 0, 0);
+                        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai2, xb[5][t], c0, 0, 0, 0);
+                        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar1, xb[1][t], c1, 0, 0, 0);
+                        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai1, xb[0][t], c1, 0, 0, 0);
+                        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar2, xb[5][t], c1, 0, 0, 0);
+                        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai2, xb[4][t], c1, 0, 0, 0);
+                        // Re C2 = Ar1 B2r - Ai1 B2i + Ar2 Er - Ai2 Ei ; Im C2 = Ar1 B2i + Ai1 B2r + Ar2 Ei + Ai2 Er
+                        c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar1, xb[2][t], c2, 0, 0, 0);
+                        c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai1, xb[3][t], c2, 0, 0, 0);
+                        c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar2, xb[6][t], c2, 0, 0, 0);
+                        c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai2, xb[7][t], c2, 0, 0, 0);
+                        c3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar1, xb[3][t], c3, 0, 0, 0);
+                        c3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai1, xb[2][t], c3, 0, 0, 0);
+                        c3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar2, xb[7][t], c3, 0, 0, 0);
+                        c3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai2, xb[6][t], c3, 0, 0, 0);
+                    }
+                    acc[0][mb][nb] = c0; acc[1][mb][nb] = c1; acc[2][mb][nb] = c2; acc[3][mb][nb] = c3;
+                }
+            } else {
+                V8 bh[8], bl[8];
+#pragma unroll
+                for (int pl = 0; pl < 8; ++pl) split8<H>(xb[pl], bh[pl], bl[pl]);
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    float xa[4][8];
+                    load_a(b, mb, c, mask, xa);
+                    V8 ah[4], al[4];
+#pragma unroll
+                    for (int pl = 0; pl < 4; ++pl) split8<H>(xa[pl], ah[pl], al[pl]);
+                    const V8 nh1 = neg8(ah[1]), nl1 = neg8(al[1]);
+                    const V8 nh3 = neg8(ah[3]), nl3 = neg8(al[3]);
+                    v16f c0 = acc[0][mb][nb], c1 = acc[1][mb][nb], c2 = acc[2][mb][nb], c3 = acc[3][mb][nb];
+#define QT_SPLIT3(ACC, XH, XL, YI)                      \
+    ACC = mfma16<H>(XL, bh[YI], ACC);                   \
+    ACC = mfma16<H>(XH, bl[YI], ACC);                   \
+    ACC = mfma16<H>(XH, bh[YI], ACC);
+                    QT_SPLIT3(c0, ah[0], al[0], 0) QT_SPLIT3(c0, nh1, nl1, 1)
+                    QT_SPLIT3(c0, ah[2], al[2], 4) QT_SPLIT3(c0, nh3, nl3, 5)
+                    QT_SPLIT3(c1, ah[0], al[0], 1) QT_SPLIT3(c1, ah[1], al[1], 0)
+                    QT_SPLIT3(c1, ah[2], al[2], 5) QT_SPLIT3(c1, ah[3], al[3], 4)
+                    QT_SPLIT3(c2, ah[0], al[0], 2) QT_SPLIT3(c2, nh1, nl1, 3)
+                    QT_SPLIT3(c2, ah[2], al[2], 6) QT_SPLIT3(c2, nh3, nl3, 7)
+                    QT_SPLIT3(c3, ah[0], al[0], 3) QT_SPLIT3(c3, ah[1], al[1], 2)
+                    QT_SPLIT3(c3, ah[2], al[2], 7) QT_SPLIT3(c3, ah[3], al[3], 6)
+#undef QT_SPLIT3
+                    acc[0][mb][nb] = c0; acc[1][mb][nb] = c1; acc[2][mb][nb] = c2; acc[3][mb][nb] = c3;
+                }
+            }
+        }
+    };
+
+    issue(0, 0);
+    for (int c = 0; c < nchunks; ++c) {
+        __builtin_amdgcn_s_waitcnt(0);       // this wave's DMA of chunk c has landed
+        __syncthreads();                     // ... and every wave's; chunk c - 1 is consumed
+        if (c + 1 < nchunks) issue(c + 1, (c + 1) & 1);
+        const bool mask = edge_tile || (c * KT + KT > a.n);
+        if (mask) compute(c, c & 1, true);
+        else compute(c, c & 1, false);
+    }
+    __syncthreads();                         // LDS may be reused by the next tile
+    store_tile<MB, NB>(a, f, m0 + wm * (MT / 2), n0 + wn * (NT / 2), acc,
+                       (MODE == 0) ? 1.f : 1.f / (sa * sb), lane);
+}
 
 }  // namespace detail
 }  // namespace qt
