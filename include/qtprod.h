@@ -71,8 +71,10 @@ typedef enum {
     QT_SPLIT_BF16 = 1,  /* FP32 FFTs; facewise products as bf16 hi+lo split:
                            x = hi + lo, product ~ hi*hi + hi*lo + lo*hi on bf16 MFMA,
                            FP32 accumulate */
-    QT_SPLIT_FP16 = 2,  /* as QT_SPLIT_BF16 with fp16 hi+lo and a power-of-two
-                           scale per operand plane and frequency */
+    QT_SPLIT_FP16 = 2,  /* as QT_SPLIT_BF16 with fp16 hi+lo; operands scaled by a
+                           power of two per frequency (A^[f]) and per frequency
+                           pair (B^[f], B^[-f]) computed on the device; qt_tprod
+                           only (the other entry points return QT_ERR_UNSUPPORTED) */
     QT_FP64 = 3         /* every step in double (small problems, validation) */
 } qt_precision;
 

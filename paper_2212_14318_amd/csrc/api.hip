@@ -49,7 +49,7 @@ size_t fourier_bytes(long rows, long cols, long p, int prec) {
 
 bool p_supported(int p, int prec) {
     if (p < 1 || p > QT_MAX_P) return false;
-    if (prec == QT_SPLIT_FP16) return false;   // not served by this build
+
     return prec == QT_FP64 ? qt::tube_fft_supported<double>(p) : qt::tube_fft_supported<float>(p);
 }
 
@@ -127,6 +127,20 @@ int run_tprod(int m, int n, int s, int p, const T* A, const T* B, T* C, int prec
 
     // step 2: coupled facewise products
     FacewiseArgs<T> fa{Ah, Bh, Ch, m, n, s, p, lda, ldb, ldc};
+    if constexpr (sizeof(T) == 4) {
+        if (prec == QT_SPLIT_FP16) {
+            char* sc = ws + fourier_bytes(m, n, p, prec) + fourier_bytes(n, s, p, prec) +
+                       fourier_bytes(m, s, p, prec);
+            float* scales = reinterpret_cast<float*>(sc);
+            float* partials = scales + 2 * (size_t)p;
+            st = hip_status(qt::launch_fp16_scales(fa, partials, scales, stream));
+            if (st != QT_OK) return st;
+            st = hip_status(qt::launch_facewise_f32(fa, prec, stream, qt::choose_tile(m, n, s, prec), scales));
+            if (st != QT_OK) return st;
+            FftJob<T> inv16[1] = {{Ch, C, m, s, ldc, s}};
+            return hip_status(qt::launch_tube_fft<T>(p, true, inv16, 1, tw, stream));
+        }
+    }
     st = hip_status(facewise<T>(fa, prec, stream));
     if (st != QT_OK) return st;
 
@@ -271,6 +285,7 @@ int qt_fourier_tprod(int m, int n, int s, int p, const void* Ah, int lda, const 
         return QT_ERR_INVALID_ARG;
     if (lda < n || ldb < s || ldc < s) return QT_ERR_INVALID_ARG;
     if (precision != QT_FP64 && ((lda | ldb | ldc) & 3)) return QT_ERR_INVALID_ARG;
+    if (precision == QT_SPLIT_FP16) return QT_ERR_UNSUPPORTED;   // needs scales: use qt_tprod
     if (!dims_ok(m, lda, p) || !dims_ok(n, ldb, p) || !dims_ok(m, ldc, p)) return QT_ERR_INVALID_ARG;
     const size_t cb = tensor_bytes(m, ldc, p, precision);
     if (overlaps(Ch, cb, Ah, tensor_bytes(m, lda, p, precision)) ||
@@ -293,8 +308,12 @@ int qt_fourier_tprod(int m, int n, int s, int p, const void* Ah, int lda, const 
 size_t qt_workspace_size(int m, int n, int s, int p, int precision) {
     if (!valid_precision(precision) || !dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p))
         return 0;
-    return fourier_bytes(m, n, p, precision) + fourier_bytes(n, s, p, precision) +
-           fourier_bytes(m, s, p, precision);
+    size_t total = fourier_bytes(m, n, p, precision) + fourier_bytes(n, s, p, precision) +
+                   fourier_bytes(m, s, p, precision);
+    if (precision == QT_SPLIT_FP16)    // scales (2p floats) and max-abs partials
+        total += align_up(sizeof(float) * (size_t)p *
+                          (2 + qt::fp16_partial_blocks(m, n) + qt::fp16_partial_blocks(n, s)));
+    return total;
 }
 
 int qt_tprod(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision,
@@ -345,7 +364,7 @@ int qt_tprod_backward(int m, int n, int s, int p, const void* A, const void* B, 
         if (dB && overlaps(dB, bb, ins[q], insz[q])) return QT_ERR_INVALID_ARG;
     }
     if (dA && dB && overlaps(dA, ab, dB, bb)) return QT_ERR_INVALID_ARG;
-    if (!p_supported(p, precision)) return QT_ERR_UNSUPPORTED;
+    if (!p_supported(p, precision) || precision == QT_SPLIT_FP16) return QT_ERR_UNSUPPORTED;
     if (!dA && !dB) return QT_OK;
     if (precision == QT_FP64)
         return run_backward<double>(m, n, s, p, (const double*)A, (const double*)B, (const double*)G,

@@ -59,10 +59,12 @@ double tile_cost(const TuneTable& t, int cfg, int n) {
     return t.alpha[cfg] + t.beta[cfg] * (double)((n + 15) / 16);
 }
 
-int pick_tile(const TuneTable* t, int m, int n, int s) {
+// allowed: bit mask of tile shapes to choose from
+int pick_tile(const TuneTable* t, int m, int n, int s, unsigned allowed = 0xffu) {
     int best = detail::TILE_128x64;
     double best_cost = 1e300;
     for (int cfg = 0; cfg < NUM_TILE_CFGS; ++cfg) {
+        if (!((allowed >> cfg) & 1u)) continue;
         const double tiles = (double)((m + tile_mt(cfg) - 1) / tile_mt(cfg)) *
                              (double)((s + tile_nt(cfg) - 1) / tile_nt(cfg));
         // untuned: padded area as the cost (prefers the least waste)
@@ -330,7 +332,9 @@ int build_lists(int count, const qt_problem* probs, int prec, char* ws, const De
         H->fwd_jobs.push_back(BatchFftJob{(const float*)q.A, Ah, tw.f32, q.m, q.n, q.n, lda, q.p, pol});
         H->fwd_jobs.push_back(BatchFftJob{(const float*)q.B, Bh, tw.f32, q.n, q.s, q.s, ldb, q.p, pol});
         H->inv_jobs.push_back(BatchFftJob{Ch, (float*)q.C, tw.f32, q.m, q.s, ldc, q.s, q.p, pol});
-        const int cfg = pick_tile(&tune, q.m, q.n, q.s);
+        // the persistent kernel carries the 128x64 and 64x64 shapes
+        const int cfg = pick_tile(&tune, q.m, q.n, q.s,
+                                  (1u << detail::TILE_128x64) | (1u << detail::TILE_64x64));
         H->probs.push_back(BatchGemmProb{FacewiseArgs<float>{Ah, Bh, Ch, q.m, q.n, q.s, q.p, lda, ldb, ldc},
                                          cfg, 0, 0, 0});
     }

@@ -104,7 +104,77 @@ __global__ void __launch_bounds__(256) facewise_f64_valu(FacewiseArgs<double> a)
     }
 }
 
+// ------------------------------------------------ fp16 power-of-two scales
+// fp16 has a 5-bit exponent, so the split operands are scaled by a power of
+// two before the split: per frequency f, sa[f] for the four planes of A^[f],
+// and sb[f] for the eight B planes of the pair {f, -f}, chosen so that the
+// largest magnitude lands in [2^14, 2^15) (hi <= 65504 with room, lo keeps
+// 11 more bits).  Powers of two make the scaling exact; the product is
+// multiplied back by 1 / (sa sb).  Max-abs is a deterministic two-pass
+// reduction (per-block partials, then one thread per frequency).
+__global__ void __launch_bounds__(256)
+absmax_partial_kernel(const float* __restrict__ X, int rows, int cols, int ld, int p, int nblk,
+                      float* __restrict__ partial) {
+    __shared__ float red[256];
+    const int f = blockIdx.y;
+    const size_t face = (size_t)rows * ld, plane = (size_t)p * face;
+    const float* Xf = X + (size_t)f * face;
+    float mx = 0.f;
+    const long count = (long)rows * cols;
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < count; e += (long)nblk * 256) {
+        const int i = (int)(e / cols), j = (int)(e - (long)i * cols);
+        const size_t off = (size_t)i * ld + j;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) mx = fmaxf(mx, fabsf(Xf[c * plane + off]));
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(size_t)f * nblk + blockIdx.x] = red[0];
+}
+
+__device__ __forceinline__ float pow2_scale(float mx) {
+    if (!(mx > 0.f) || !isfinite(mx)) return 1.f;
+    int e;
+    (void)frexpf(mx, &e);                 // mx < 2^e
+    return ldexpf(1.f, 15 - e);           // mx * scale < 2^15
+}
+
+__global__ void fp16_scales_kernel(const float* __restrict__ pa, int nba, const float* __restrict__ pb,
+                                   int nbb, int p, float* __restrict__ scales) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= p) return;
+    const int g = (p - f) % p;
+    float ma = 0.f, mb = 0.f;
+    for (int b = 0; b < nba; ++b) ma = fmaxf(ma, pa[(size_t)f * nba + b]);
+    for (int b = 0; b < nbb; ++b) mb = fmaxf(mb, fmaxf(pb[(size_t)f * nbb + b], pb[(size_t)g * nbb + b]));
+    scales[f] = pow2_scale(ma);
+    scales[p + f] = pow2_scale(mb);
+}
+
 }  // namespace
+
+int fp16_partial_blocks(long rows, long cols) {
+    const long b = (rows * cols + 255) / 256;
+    return (int)(b < 64 ? b : 64);
+}
+
+hipError_t launch_fp16_scales(const FacewiseArgs<float>& a, float* partials, float* scales,
+                              hipStream_t stream) {
+    const int nba = fp16_partial_blocks(a.m, a.n), nbb = fp16_partial_blocks(a.n, a.s);
+    float* pa = partials;
+    float* pb = partials + (size_t)a.p * nba;
+    hipLaunchKernelGGL(absmax_partial_kernel, dim3(nba, a.p), dim3(256), 0, stream, a.Ah, a.m, a.n, a.lda,
+                       a.p, nba, pa);
+    hipLaunchKernelGGL(absmax_partial_kernel, dim3(nbb, a.p), dim3(256), 0, stream, a.Bh, a.n, a.s, a.ldb,
+                       a.p, nbb, pb);
+    hipLaunchKernelGGL(fp16_scales_kernel, dim3((a.p + 255) / 256), dim3(256), 0, stream, pa, nba, pb, nbb,
+                       a.p, scales);
+    return hipGetLastError();
+}
 
 template <int CFG>
 static hipError_t launch_cfg(const FacewiseArgs<float>& a, int precision, const float* scales,

@@ -29,25 +29,6 @@ namespace detail {
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int KT = 16;     // k-chunk depth
-constexpr int APAD = 4;    // row padding of the k-major FP32 A chunk
-constexpr int SRS = 40;    // LDS row stride of the split chunks, in 16-bit values
-
-template <int MT, int NT>
-struct F32Smem {
-    float A[4][KT][MT + APAD];   // k-major A chunk (4 planes)
-    float B[8][KT][NT];          // B chunk: 4 planes at f, 4 at g
-};
-
-__device__ __forceinline__ float4 masked_load4(const float* p, bool row_ok, int c0, int limit) {
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (row_ok && c0 < limit) {
-        v = *reinterpret_cast<const float4*>(p);
-        if (c0 + 1 >= limit) v.y = 0.f;
-        if (c0 + 2 >= limit) v.z = 0.f;
-        if (c0 + 3 >= limit) v.w = 0.f;
-    }
-    return v;
-}
 
 // 32x32 f32 accumulator layout of v_mfma_f32_32x32x*: register r of lane l
 // holds row 8 (r / 4) + 4 (l / 32) + (r % 4), column l % 32.
@@ -75,142 +56,18 @@ __device__ __forceinline__ void store_tile(const FacewiseArgs<float>& a, int f, 
     }
 }
 
-// ---------------------------------------------------------------- FP32 MFMA
-// v_mfma_f32_32x32x2_f32; each wave owns (MT/2) x (NT/2) = MB x NB blocks.
-template <int MT, int NT>
-__device__ __forceinline__ void tile_f32(const FacewiseArgs<float>& a, int f, int m0, int n0,
-                                         F32Smem<MT, NT>& sm) {
-    constexpr int MB = MT / 64, NB = NT / 64;
-    constexpr int NLA = MT / 16, NLB = NT / 8;       // float4 loads per thread
-    const int tid = threadIdx.x;
-    const int g = (a.p - f) % a.p;
-    const size_t pa = (size_t)a.p * a.m * a.lda;
-    const size_t pb = (size_t)a.p * a.n * a.ldb;
-    const float* Af = a.Ah + (size_t)f * a.m * a.lda;
-    const float* Bf = a.Bh + (size_t)f * a.n * a.ldb;
-    const float* Bg = a.Bh + (size_t)g * a.n * a.ldb;
-
-    float4 ra[NLA], rb[NLB];
-    auto load_global = [&](int k0) {
-#pragma unroll
-        for (int it = 0; it < NLA; ++it) {
-            const int idx = tid + 256 * it;
-            const int pl = idx / (4 * MT), rem = idx % (4 * MT);
-            const int row = rem >> 2, kq = rem & 3;
-            const int grow = m0 + row, gk = k0 + 4 * kq;
-            ra[it] = masked_load4(Af + pl * pa + (size_t)grow * a.lda + gk, grow < a.m, gk, a.n);
-        }
-#pragma unroll
-        for (int it = 0; it < NLB; ++it) {
-            const int idx = tid + 256 * it;
-            const int pl = idx / (4 * NT), rem = idx % (4 * NT);
-            const int kr = rem / (NT / 4), nq = rem % (NT / 4);
-            const int gk = k0 + kr, gc = n0 + 4 * nq;
-            const float* src = (pl < 4 ? Bf + pl * pb : Bg + (pl - 4) * pb);
-            rb[it] = masked_load4(src + (size_t)gk * a.ldb + gc, gk < a.n, gc, a.s);
-        }
-    };
-    auto store_lds = [&]() {
-#pragma unroll
-        for (int it = 0; it < NLA; ++it) {
-            const int idx = tid + 256 * it;
-            const int pl = idx / (4 * MT), rem = idx % (4 * MT);
-            const int row = rem >> 2, kq = rem & 3;
-            sm.A[pl][4 * kq + 0][row] = ra[it].x;
-            sm.A[pl][4 * kq + 1][row] = ra[it].y;
-            sm.A[pl][4 * kq + 2][row] = ra[it].z;
-            sm.A[pl][4 * kq + 3][row] = ra[it].w;
-        }
-#pragma unroll
-        for (int it = 0; it < NLB; ++it) {
-            const int idx = tid + 256 * it;
-            const int pl = idx / (4 * NT), rem = idx % (4 * NT);
-            const int kr = rem / (NT / 4), nq = rem % (NT / 4);
-            *reinterpret_cast<float4*>(&sm.B[pl][kr][4 * nq]) = rb[it];
-        }
-    };
-
-    const int wave = tid >> 6, lane = tid & 63;
-    const int wm = wave & 1, wn = wave >> 1;
-    const int lr = lane & 31, lk = lane >> 5;
-
-    v16f acc[4][MB][NB];
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc[c][mb][nb][r] = 0.f;
-
-    load_global(0);
-    store_lds();
-    __syncthreads();
-    for (int k0 = 0; k0 < a.n; k0 += KT) {
-        const bool more = k0 + KT < a.n;
-        if (more) load_global(k0 + KT);
-#pragma unroll
-        for (int kk = 0; kk < KT / 2; ++kk) {
-            const int k = 2 * kk + lk;
-            float bf[8][NB];
-#pragma unroll
-            for (int c = 0; c < 8; ++c)
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) bf[c][nb] = sm.B[c][k][wn * (NT / 2) + nb * 32 + lr];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                const int r = wm * (MT / 2) + mb * 32 + lr;
-                const float ar1 = sm.A[0][k][r], ai1 = sm.A[1][k][r];
-                const float ar2 = sm.A[2][k][r], ai2 = sm.A[3][k][r];
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) {
-                    v16f c0 = acc[0][mb][nb], c1 = acc[1][mb][nb], c2 = acc[2][mb][nb], c3 = acc[3][mb][nb];
-                    c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar1, bf[0][nb], c0, 0, 0, 0);
-                    c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai1, bf[1][nb], c0, 0, 0, 0);
-                    c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(-ar2, bf[6][nb], c0, 0, 0, 0);
-                    c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai2, bf[7][nb], c0, 0, 0, 0);
-                    c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar1, bf[1][nb], c1, 0, 0, 0);
-                    c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai1, bf[0][nb], c1, 0, 0, 0);
-                    c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar2, bf[7][nb], c1, 0, 0, 0);
-                    c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai2, bf[6][nb], c1, 0, 0, 0);
-                    c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar1, bf[2][nb], c2, 0, 0, 0);
-                    c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai1, bf[3][nb], c2, 0, 0, 0);
-                    c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar2, bf[4][nb], c2, 0, 0, 0);
-                    c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai2, bf[5][nb], c2, 0, 0, 0);
-                    c3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar1, bf[3][nb], c3, 0, 0, 0);
-                    c3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai1, bf[2][nb], c3, 0, 0, 0);
-                    c3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai2, bf[4][nb], c3, 0, 0, 0);
-                    c3 = __builtin_amdgcn_mfma_f32_32x32x2f32(-ar2, bf[5][nb], c3, 0, 0, 0);
-                    acc[0][mb][nb] = c0; acc[1][mb][nb] = c1; acc[2][mb][nb] = c2; acc[3][mb][nb] = c3;
-                }
-            }
-        }
-        __syncthreads();
-        if (more) {
-            store_lds();
-            __syncthreads();
-        }
-    }
-    store_tile<MB, NB>(a, f, m0 + wm * (MT / 2), n0 + wn * (NT / 2), acc, 1.f, lane);
-}
-
 // ------------------------------------------------------ split bf16 / fp16
 // x = hi + lo with hi = rn(x), lo = rn(x - hi) in a 16-bit format; a real
 // product X Y is taken as Xhi Yhi + Xhi Ylo + Xlo Yhi (the dropped Xlo Ylo is
 // ~2^-16 relative for bf16), each on v_mfma_f32_32x32x16_{bf16,f16} with FP32
-// accumulation.  The split happens while a chunk is staged into LDS, so the
-// Fourier-domain tensors stay FP32 in HBM (same bytes as the FP32 path).
+// accumulation.  The Fourier-domain tensors stay FP32 in HBM (same bytes as
+// the FP32 path); the split happens when MFMA fragments are formed.
 //
 // The coupled products are rewritten as two plain complex products,
 //   C1^ = A1^ B1^[f] + A2^ D,  D = -conj(B2^[g]),
 //   C2^ = A1^ B2^[f] + A2^ E,  E =  conj(B1^[g]),
-// whose signs are applied to the B chunk when it is staged, so that every real
-// term adds: Re = Xr Yr + (-Xi) Yi, Im = Xr Yi + Xi Yr.
-//
-// LDS holds both operands k-contiguous (a row of A, a column of B): 16 hi
-// values, 16 lo values and 8 padding values per row/column, so one lane reads
-// its 8 consecutive k of hi (or lo) with a single 16-byte load.
+// whose signs are applied to the B fragments, so that every real term adds:
+// Re = Xr Yr + (-Xi) Yi, Im = Xr Yi + Xi Yr.
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
@@ -238,157 +95,6 @@ __device__ __forceinline__ V8 neg8(V8 x) {
     u4 b = __builtin_bit_cast(u4, x);
     b ^= 0x80008000u;
     return __builtin_bit_cast(V8, b);
-}
-
-template <typename H, int MT, int NT>
-struct SplitSmem {
-    H A[4][MT][SRS];
-    H B[8][NT][SRS];
-};
-
-// sa, sb: power-of-two scales applied before the split (1 for bf16, whose
-// range is FP32's; per frequency for fp16); the result is multiplied by
-// 1 / (sa sb).
-template <typename H, int MT, int NT>
-__device__ __forceinline__ void tile_split(const FacewiseArgs<float>& a, int f, int m0, int n0,
-                                           float sa, float sb, SplitSmem<H, MT, NT>& sm) {
-    using V8 = typename SplitTypes<H>::v8;
-    using V4 = typename SplitTypes<H>::v4;
-    constexpr int MB = MT / 64, NB = NT / 64;
-    constexpr int NH = MT / 16, NCG = NT / 64;
-    const int tid = threadIdx.x;
-    const int g = (a.p - f) % a.p;
-    const size_t pa = (size_t)a.p * a.m * a.lda;
-    const size_t pb = (size_t)a.p * a.n * a.ldb;
-    const float* Af = a.Ah + (size_t)f * a.m * a.lda;
-    const float* Bf = a.Bh + (size_t)f * a.n * a.ldb;
-    const float* Bg = a.Bh + (size_t)g * a.n * a.ldb;
-
-    // A chunk: plane = tid / 64; 4 lanes cover the 16 k of one row
-    const int a_pl = tid >> 6, a_kq = tid & 3, a_r0 = (tid & 63) >> 2;
-    // B chunk: plane = tid / 32; 16 lanes cover 64 columns, 2 halves of 8 k rows
-    const int b_pl = tid >> 5, b_cq = tid & 15, b_kh = (tid & 31) >> 4;
-    // source plane and sign of the staged B plane (0..3: B^[f]; 4..7: D, E from B^[g])
-    const int b_src = b_pl < 4 ? b_pl : (b_pl == 4 ? 2 : b_pl == 5 ? 3 : b_pl == 6 ? 0 : 1);
-    const float b_scale = ((b_pl == 4 || b_pl == 7) ? -1.f : 1.f) * sb;
-    const float* b_base = (b_pl < 4 ? Bf : Bg) + b_src * pb;
-    const float* a_base = Af + a_pl * pa;
-
-    float4 ra[NH], rb[NCG][8];
-    auto load_global = [&](int k0) {
-#pragma unroll
-        for (int h = 0; h < NH; ++h) {
-            const int grow = m0 + a_r0 + 16 * h, gk = k0 + 4 * a_kq;
-            ra[h] = masked_load4(a_base + (size_t)grow * a.lda + gk, grow < a.m, gk, a.n);
-        }
-#pragma unroll
-        for (int cg = 0; cg < NCG; ++cg)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int gk = k0 + 8 * b_kh + j, gc = n0 + 64 * cg + 4 * b_cq;
-                rb[cg][j] = masked_load4(b_base + (size_t)gk * a.ldb + gc, gk < a.n, gc, a.s);
-            }
-    };
-    auto store_lds = [&]() {
-#pragma unroll
-        for (int h = 0; h < NH; ++h) {
-            const float x[4] = {ra[h].x * sa, ra[h].y * sa, ra[h].z * sa, ra[h].w * sa};
-            V4 hi, lo;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                hi[q] = (H)x[q];
-                lo[q] = (H)(x[q] - (float)hi[q]);
-            }
-            H* row = &sm.A[a_pl][a_r0 + 16 * h][0];
-            *reinterpret_cast<V4*>(row + 4 * a_kq) = hi;
-            *reinterpret_cast<V4*>(row + 16 + 4 * a_kq) = lo;
-        }
-#pragma unroll
-        for (int cg = 0; cg < NCG; ++cg)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                V8 hi, lo;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const float4 v = rb[cg][j];
-                    const float x = (c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w) * b_scale;
-                    hi[j] = (H)x;
-                    lo[j] = (H)(x - (float)hi[j]);
-                }
-                H* col = &sm.B[b_pl][64 * cg + 4 * b_cq + c][0];
-                *reinterpret_cast<V8*>(col + 8 * b_kh) = hi;
-                *reinterpret_cast<V8*>(col + 16 + 8 * b_kh) = lo;
-            }
-    };
-
-    const int wave = tid >> 6, lane = tid & 63;
-    const int wm = wave & 1, wn = wave >> 1;
-    const int lr = lane & 31, lk = lane >> 5;
-
-    v16f acc[4][MB][NB];
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc[c][mb][nb][r] = 0.f;
-
-    load_global(0);
-    store_lds();
-    __syncthreads();
-    for (int k0 = 0; k0 < a.n; k0 += KT) {
-        const bool more = k0 + KT < a.n;
-        if (more) load_global(k0 + KT);
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            V8 bh[8], bl[8];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const H* col = &sm.B[c][wn * (NT / 2) + nb * 32 + lr][0];
-                bh[c] = *reinterpret_cast<const V8*>(col + 8 * lk);
-                bl[c] = *reinterpret_cast<const V8*>(col + 16 + 8 * lk);
-            }
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                V8 ah[4], al[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const H* row = &sm.A[c][wm * (MT / 2) + mb * 32 + lr][0];
-                    ah[c] = *reinterpret_cast<const V8*>(row + 8 * lk);
-                    al[c] = *reinterpret_cast<const V8*>(row + 16 + 8 * lk);
-                }
-                const V8 nh1 = neg8(ah[1]), nl1 = neg8(al[1]);   // -Ai1
-                const V8 nh3 = neg8(ah[3]), nl3 = neg8(al[3]);   // -Ai2
-                v16f c0 = acc[0][mb][nb], c1 = acc[1][mb][nb], c2 = acc[2][mb][nb], c3 = acc[3][mb][nb];
-#define QT_SPLIT3(ACC, XH, XL, YI)                      \
-    ACC = mfma16<H>(XL, bh[YI], ACC);                   \
-    ACC = mfma16<H>(XH, bl[YI], ACC);                   \
-    ACC = mfma16<H>(XH, bh[YI], ACC);
-                // Re C1 = Ar1 B1r + (-Ai1) B1i + Ar2 Dr + (-Ai2) Di
-                QT_SPLIT3(c0, ah[0], al[0], 0) QT_SPLIT3(c0, nh1, nl1, 1)
-                QT_SPLIT3(c0, ah[2], al[2], 4) QT_SPLIT3(c0, nh3, nl3, 5)
-                // Im C1 = Ar1 B1i + Ai1 B1r + Ar2 Di + Ai2 Dr
-                QT_SPLIT3(c1, ah[0], al[0], 1) QT_SPLIT3(c1, ah[1], al[1], 0)
-                QT_SPLIT3(c1, ah[2], al[2], 5) QT_SPLIT3(c1, ah[3], al[3], 4)
-                // Re C2 = Ar1 B2r + (-Ai1) B2i + Ar2 Er + (-Ai2) Ei
-                QT_SPLIT3(c2, ah[0], al[0], 2) QT_SPLIT3(c2, nh1, nl1, 3)
-                QT_SPLIT3(c2, ah[2], al[2], 6) QT_SPLIT3(c2, nh3, nl3, 7)
-                // Im C2 = Ar1 B2i + Ai1 B2r + Ar2 Ei + Ai2 Er
-                QT_SPLIT3(c3, ah[0], al[0], 3) QT_SPLIT3(c3, ah[1], al[1], 2)
-                QT_SPLIT3(c3, ah[2], al[2], 7) QT_SPLIT3(c3, ah[3], al[3], 6)
-#undef QT_SPLIT3
-                acc[0][mb][nb] = c0; acc[1][mb][nb] = c1; acc[2][mb][nb] = c2; acc[3][mb][nb] = c3;
-            }
-        }
-        __syncthreads();
-        if (more) {
-            store_lds();
-            __syncthreads();
-        }
-    }
-    store_tile<MB, NB>(a, f, m0 + wm * (MT / 2), n0 + wn * (NT / 2), acc, 1.f / (sa * sb), lane);
 }
 
 // Tile shapes (MT x NT) compiled for both kernels; the id is what the

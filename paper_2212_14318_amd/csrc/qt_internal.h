@@ -66,6 +66,13 @@ hipError_t launch_facewise_f32(const FacewiseArgs<float>& a, int precision, hipS
                                int tile_cfg = 0, const float* scales = nullptr);
 hipError_t launch_facewise_f64(const FacewiseArgs<double>& a, hipStream_t stream);
 
+// fp16 split: per-frequency power-of-two scales of A^ and of the B^ pairs
+// {f, -f} into scales[0 .. 2p); partials needs p * (fp16_partial_blocks(m, n) +
+// fp16_partial_blocks(n, s)) floats.
+int fp16_partial_blocks(long rows, long cols);
+hipError_t launch_fp16_scales(const FacewiseArgs<float>& a, float* partials, float* scales,
+                              hipStream_t stream);
+
 // Tensor conjugate transpose job: src is rows x cols x p ([4][p][rows][cols]),
 // dst is cols x rows x p.  planes_faces is filled in by the launcher.
 template <typename T>

@@ -23,7 +23,8 @@ FP64_TOL = 1e-13
 # cannot meet.
 SPLIT_GATE = 2e-3
 SPLIT_GUARD = 5e-5
-TOLS = {"fp32": FP32_TOL, "split_bf16": SPLIT_GUARD}
+TOLS = {"fp32": FP32_TOL, "split_bf16": SPLIT_GUARD, "split_fp16": SPLIT_GUARD}
+PRECS = ["fp32", "split_bf16", "split_fp16"]
 
 
 # ------------------------------------------------------------------ tube FFT
@@ -69,7 +70,7 @@ def test_c1_fp32():
 
 # Several GEMM tiles in m and s with ragged tails, several k-chunks with a
 # ragged tail, and every kind of p (odd, even, prime factors 2/3/5/7).
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("p", [1, 2, 3, 5, 7, 8, 12, 16, 30, 32])
 def test_parity_ragged_full(p, prec):
     m, n, s = 300, 50, 150
@@ -81,7 +82,7 @@ def test_parity_ragged_full(p, prec):
     assert err <= TOLS[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("p", [45, 64, 100, 128])
 def test_parity_ragged_faces(p, prec):
     m, n, s = 260, 36, 140
@@ -102,8 +103,9 @@ def test_edge_shapes(m, n, s, p):
     ref = oracle.tprod(A, B)
     C32 = to_np(tprod(to_dev(A), to_dev(B)))
     assert rel_err(C32, ref) <= FP32_TOL
-    Cs = to_np(tprod(to_dev(A), to_dev(B), precision="split_bf16"))
-    assert rel_err(Cs, ref) <= SPLIT_GUARD
+    for prec in ("split_bf16", "split_fp16"):
+        Cs = to_np(tprod(to_dev(A), to_dev(B), precision=prec))
+        assert rel_err(Cs, ref) <= SPLIT_GUARD
     C64 = to_np(tprod(to_dev(A, torch.float64), to_dev(B, torch.float64), precision="fp64"))
     assert rel_err(C64, ref) <= FP64_TOL
 
@@ -123,7 +125,7 @@ def test_identity_tensor_gpu():
     assert rel_err(C, A) <= FP32_TOL
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("prec", PRECS)
 def test_deterministic(prec):
     A = synth.quat_tensor(200, 64, 16, seed=904)
     B = synth.quat_tensor(64, 100, 16, seed=905)
@@ -133,7 +135,7 @@ def test_deterministic(prec):
     assert torch.equal(C1, C2)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("prec", PRECS)
 def test_nan_propagates(prec):
     A = synth.quat_tensor(16, 8, 4, seed=906)
     B = synth.quat_tensor(8, 16, 4, seed=907)
@@ -141,6 +143,19 @@ def test_nan_propagates(prec):
     C = to_np(tprod(to_dev(A), to_dev(B), precision=prec))
     assert np.isnan(C[:, :, 3, :]).all()          # row 3 of every face is poisoned
     assert np.isfinite(np.delete(C, 3, axis=2)).all()
+
+
+def test_fp16_scaling_handles_wide_range():
+    """Faces spanning 1e-3..1e3 and a tensor of magnitude 1e6: the per-frequency
+    power-of-two scales keep fp16 hi/lo in range."""
+    m, n, s, p = 96, 40, 70, 12
+    w = synth.face_scales(p)[None, :, None, None]
+    A = synth.quat_tensor(m, n, p, seed=950) * w * 1e3
+    B = synth.quat_tensor(n, s, p, seed=951) * w * 1e3
+    C = to_np(tprod(to_dev(A), to_dev(B), precision="split_fp16"))
+    err = rel_err(C, oracle.tprod_faces(A, B))
+    print(f"fp16 wide range rel err {err:.3e}")
+    assert err <= SPLIT_GUARD
 
 
 def test_status_errors_raise():
@@ -166,9 +181,9 @@ def test_c3_full_size_sampled(draw):
     A, B = synth.config_inputs(3, draw=draw)
     Ad, Bd = to_dev(A), to_dev(B)
     k, i, j = sample_indices(32, 1024, 1024, 12, seed=3100 + draw, per_face=True)
-    for prec in ("fp32", "split_bf16"):
+    for prec in PRECS:
         C = to_np(tprod(Ad, Bd, precision=prec))
         err = sampled_rel_err(C, A, B, k, i, j)
         print(f"c3 draw {draw} {prec} sampled rel err {err:.3e}")
         assert err <= TOLS[prec]
-        assert err <= (SPLIT_GATE if prec == "split_bf16" else FP32_TOL)
+        assert err <= (SPLIT_GATE if prec.startswith("split") else FP32_TOL)
