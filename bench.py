@@ -124,9 +124,11 @@ def main():
         del src, dst
 
     def stage_calls(prec_id, ev):
-        st = nat.qt_tube_fft(m, n, p, A.data_ptr(), n, Ah.data_ptr(), lda, 0, nat.QT_FP32, sh)
+        # forward transforms in the operand format of the precision (split-bf16:
+        # hi/lo words), product, inverse transform of the FP32 product
+        st = nat.qt_tube_fft(m, n, p, A.data_ptr(), n, Ah.data_ptr(), lda, 0, prec_id, sh)
         nat.check(st, "qt_tube_fft(A)")
-        st = nat.qt_tube_fft(n, s, p, B.data_ptr(), s, Bh.data_ptr(), ldb, 0, nat.QT_FP32, sh)
+        st = nat.qt_tube_fft(n, s, p, B.data_ptr(), s, Bh.data_ptr(), ldb, 0, prec_id, sh)
         nat.check(st, "qt_tube_fft(B)")
         ev[0].record(stream)
         st = nat.qt_fourier_tprod(m, n, s, p, Ah.data_ptr(), lda, Bh.data_ptr(), ldb,

@@ -111,18 +111,24 @@ int qt_fourier_ld(int cols);
  * (ldx, ldh >= cols; entries beyond cols are neither read nor written);
  * Xh planes are (Re X1^, Im X1^, Re X2^, Im X2^).  The paper's transform of
  * Theorem 4.4 is fft(conj X) = conj(X1^[-f]) - X2^[f] j in these terms.
- * X and Xh must not overlap.  precision: QT_FP32 (float) or QT_FP64 (double);
- * the split precisions use the FP32 transform, so they are accepted as FP32. */
+ * X and Xh must not overlap.  precision: QT_FP32 (float) or QT_FP64 (double).
+ * QT_SPLIT_BF16 with inverse = 0 writes the operand format of the split-bf16
+ * facewise products instead of floats: every real x becomes the 32-bit word
+ * hi | lo << 16 with hi = rn_bf16(x), lo = rn_bf16(x - hi) (same layout and
+ * size); QT_SPLIT_FP16, and any split precision with inverse = 1, transform
+ * floats like QT_FP32. */
 int qt_tube_fft(int rows, int cols, int p, const void* X, int ldx, void* Xh, int ldh,
                 int inverse, int precision, hipStream_t stream);
 
 /* Step 2 alone, for Fourier-domain-resident chains: for every frequency f,
  *   C1^[f] = A1^[f] B1^[f] - A2^[f] conj(B2^[-f]),
  *   C2^[f] = A1^[f] B2^[f] + A2^[f] conj(B1^[-f])   (Theorem 5.1, Remark 5.1),
- * on tensors produced by qt_tube_fft: Ah [4][p][m][lda], Bh [4][p][n][ldb],
- * Ch [4][p][m][ldc] (ldc >= s, entries beyond s untouched).  For the float
- * precisions lda, ldb, ldc must be multiples of 4 (16-byte rows).
- * qt_tube_fft(inverse = 1) of Ch is then A * B.  No workspace. */
+ * on tensors produced by qt_tube_fft with the same precision (QT_SPLIT_BF16:
+ * split words): Ah [4][p][m][lda], Bh [4][p][n][ldb], Ch [4][p][m][ldc] (floats;
+ * ldc >= s, entries beyond s untouched).  For the float precisions lda, ldb,
+ * ldc must be multiples of 4 (16-byte rows).  qt_tube_fft(inverse = 1) of Ch
+ * is then A * B.  No workspace.  QT_SPLIT_FP16 needs per-call scales and is
+ * served by qt_tprod only (QT_ERR_UNSUPPORTED here). */
 int qt_fourier_tprod(int m, int n, int s, int p, const void* Ah, int lda, const void* Bh,
                      int ldb, void* Ch, int ldc, int precision, hipStream_t stream);
 

@@ -121,8 +121,10 @@ int run_tprod(int m, int n, int s, int p, const T* A, const T* B, T* C, int prec
     T* Bh = reinterpret_cast<T*>(ws + fourier_bytes(m, n, p, prec));
     T* Ch = reinterpret_cast<T*>(ws + fourier_bytes(m, n, p, prec) + fourier_bytes(n, s, p, prec));
 
-    // step 1: tube FFT of A and B (one launch)
-    FftJob<T> fwd[2] = {{A, Ah, m, n, n, lda}, {B, Bh, n, s, s, ldb}};
+    // step 1: tube FFT of A and B (one launch); split-bf16 operands leave the
+    // FFT already split into hi/lo words
+    const int pack = prec == QT_SPLIT_BF16 ? 1 : 0;
+    FftJob<T> fwd[2] = {{A, Ah, m, n, n, lda, pack}, {B, Bh, n, s, s, ldb, pack}};
     if (qt::launch_tube_fft<T>(p, false, fwd, 2, tw, stream) != hipSuccess) return QT_ERR_HIP;
 
     // step 2: coupled facewise products
@@ -201,11 +203,12 @@ int run_backward(int m, int n, int s, int p, const T* A, const T* B, const T* G,
     st = hip_status(qt::launch_conj_transpose<T>(cj, ncj, stream));
     if (st != QT_OK) return st;
 
-    FftJob<T> f1[2] = {{G, Gh, m, s, s, lds}, {Y, Yh, s, n, n, ldn}};
+    const int pack = prec == QT_SPLIT_BF16 ? 1 : 0;
+    FftJob<T> f1[2] = {{G, Gh, m, s, s, lds, pack}, {Y, Yh, s, n, n, ldn, pack}};
     st = hip_status(qt::launch_tube_fft<T>(p, false, f1, dA ? 2 : 1, tw, stream));
     if (st != QT_OK) return st;
     if (dB) {
-        FftJob<T> f2[1] = {{Z, Zh, n, m, m, ldm}};
+        FftJob<T> f2[1] = {{Z, Zh, n, m, m, ldm, pack}};
         st = hip_status(qt::launch_tube_fft<T>(p, false, f2, 1, tw, stream));
         if (st != QT_OK) return st;
     }
@@ -271,7 +274,8 @@ int qt_tube_fft(int rows, int cols, int p, const void* X, int ldx, void* Xh, int
         FftJob<double> j{(const double*)X, (double*)Xh, rows, cols, ldx, ldh};
         e = qt::launch_tube_fft<double>(p, inverse != 0, &j, 1, tw, stream);
     } else {
-        FftJob<float> j{(const float*)X, (float*)Xh, rows, cols, ldx, ldh};
+        const int pack = (precision == QT_SPLIT_BF16 && !inverse) ? 1 : 0;
+        FftJob<float> j{(const float*)X, (float*)Xh, rows, cols, ldx, ldh, pack};
         e = qt::launch_tube_fft<float>(p, inverse != 0, &j, 1, tw, stream);
     }
     return e == hipSuccess ? QT_OK : QT_ERR_HIP;

@@ -213,7 +213,7 @@ int run_tuner(int prec, hipStream_t stream, TuneTable* out) {
         if (get_twiddles(p, stream, &tw) != QT_OK) { fail = true; break; }
         double best = 1e300;
         for (int pol = 0; pol < 2; ++pol) {
-            BatchFftJob job{src, dst, tw.f32, 256, POS / 256, POS / 256, POS / 256, p, pol};
+            BatchFftJob job{src, dst, tw.f32, 256, POS / 256, POS / 256, POS / 256, p, pol, 0, 0};
             if (hipMemcpy(djob, &job, sizeof job, hipMemcpyHostToDevice) != hipSuccess) { fail = true; break; }
             hipError_t err = hipSuccess;
             const double sec = time_launch(
@@ -329,9 +329,10 @@ int build_lists(int count, const qt_problem* probs, int prec, char* ws, const De
         float* Bh = reinterpret_cast<float*>(ws + off); off += fourier_bytes(q.n, q.s, q.p);
         float* Ch = reinterpret_cast<float*>(ws + off); off += fourier_bytes(q.m, q.s, q.p);
         const int pol = tune.fft_pol[q.p];
-        H->fwd_jobs.push_back(BatchFftJob{(const float*)q.A, Ah, tw.f32, q.m, q.n, q.n, lda, q.p, pol});
-        H->fwd_jobs.push_back(BatchFftJob{(const float*)q.B, Bh, tw.f32, q.n, q.s, q.s, ldb, q.p, pol});
-        H->inv_jobs.push_back(BatchFftJob{Ch, (float*)q.C, tw.f32, q.m, q.s, ldc, q.s, q.p, pol});
+        const int pack = prec == QT_SPLIT_BF16 ? 1 : 0;
+        H->fwd_jobs.push_back(BatchFftJob{(const float*)q.A, Ah, tw.f32, q.m, q.n, q.n, lda, q.p, pol, pack, 0});
+        H->fwd_jobs.push_back(BatchFftJob{(const float*)q.B, Bh, tw.f32, q.n, q.s, q.s, ldb, q.p, pol, pack, 0});
+        H->inv_jobs.push_back(BatchFftJob{Ch, (float*)q.C, tw.f32, q.m, q.s, ldc, q.s, q.p, pol, 0, 0});
         // the persistent kernel carries the 128x64 and 64x64 shapes
         const int cfg = pick_tile(&tune, q.m, q.n, q.s,
                                   (1u << detail::TILE_128x64) | (1u << detail::TILE_64x64));

@@ -12,6 +12,7 @@ struct BatchFftJob {
     const float2* tw;          // twiddle table of p
     int rows, cols, src_ld, dst_ld;
     int p, pol;                // length and radix-order policy (0 or 1)
+    int pack, pad;             // 1: forward output as split-bf16 words (FftJob::pack)
 };
 
 // 256 consecutive positions of one CD part of one job.

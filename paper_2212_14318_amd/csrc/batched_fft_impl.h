@@ -17,7 +17,7 @@ batched_fft_kernel(const BatchFftJob* __restrict__ jobs, const BatchFftItem* __r
         const BatchFftJob bj = jobs[item.job];
         const long e = (long)item.e0 + threadIdx.x;
         if (e >= (long)bj.rows * bj.cols) continue;
-        const FftJob<float> jb{bj.src, bj.dst, bj.rows, bj.cols, bj.src_ld, bj.dst_ld};
+        const FftJob<float> jb{bj.src, bj.dst, bj.rows, bj.cols, bj.src_ld, bj.dst_ld, bj.pack};
         switch (2 * bj.p + bj.pol) {
 #define QT_BCASE(P)                                                                \
     case 2 * P: tube_fft_one<P, INV, float, 0>(jb, item.part, e, bj.tw); break;   \

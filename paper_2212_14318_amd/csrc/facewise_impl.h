@@ -121,8 +121,11 @@ __host__ __device__ constexpr int tile_nt(int cfg) { return cfg == TILE_64x128 ?
 //  * rows/columns/k beyond the problem are read from clamped (valid)
 //    addresses and zeroed before use; interior chunks skip the masks.
 // MODE 0: FP32 operands on v_mfma_f32_32x32x2_f32 (8 k-steps per chunk);
-// MODE 1/2: bf16/fp16 hi+lo split at fragment time, 3 products per term on
-// v_mfma_f32_32x32x16_{bf16,f16} (one k-step per chunk).
+// MODE 1: operands already split by the tube FFT into bf16 words hi | lo << 16
+//         (FftJob::pack), unpacked with byte permutes, 3 products per term on
+//         v_mfma_f32_32x32x16_bf16 (one k-step per chunk);
+// MODE 2: FP32 operands scaled by powers of two and split into fp16 hi + lo
+//         when the fragments are formed, on v_mfma_f32_32x32x16_f16.
 typedef __attribute__((address_space(3))) void lds_void_t;
 
 template <int MT, int NT>
@@ -143,6 +146,20 @@ __device__ __forceinline__ void split8(const float (&x)[8], typename SplitTypes<
         hi[j] = (H)x[j];
         lo[j] = (H)(x[j] - (float)hi[j]);
     }
+}
+
+// Split-bf16 operand words (hi | lo << 16, written by the tube FFT) -> the
+// hi and lo fragments of 8 consecutive k (one v_perm_b32 per pair).
+__device__ __forceinline__ void unpack8(const unsigned (&w)[8], v8bf& hi, v8bf& lo) {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    u4 h, l;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        h[j] = __builtin_amdgcn_perm(w[2 * j + 1], w[2 * j], 0x05040100u);
+        l[j] = __builtin_amdgcn_perm(w[2 * j + 1], w[2 * j], 0x07060302u);
+    }
+    hi = __builtin_bit_cast(v8bf, h);
+    lo = __builtin_bit_cast(v8bf, l);
 }
 
 template <int MODE, int MT, int NT>
@@ -192,6 +209,29 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
         }
     };
 
+    // interior chunks: uniform (scalar) base per instruction + a per-lane
+    // offset that is the same for every chunk of the tile
+    const int a_i = lane >> 2;
+    const int a_lane_off = a_i * a.lda + 4 * ((lane & 3) ^ ((a_i >> 2) & 3));
+    const int b_lane_off = (lane / CQ) * a.ldb + 4 * (lane % CQ);
+    auto issue_fast = [&](int c, int b) {
+        const int k0 = c * KT;
+#pragma unroll
+        for (int q = wave; q < 4 * ABLK; q += 4) {
+            const int pl = q / ABLK, blk = q % ABLK;
+            const float* ub = Af + pl * pa + (size_t)(m0 + blk * 16) * a.lda + k0;
+            dma16(ub + a_lane_off, &sm.A[b][pl][blk][0]);
+        }
+#pragma unroll
+        for (int q = wave; q < 8 * BBLK; q += 4) {
+            const int pl = q / BBLK, blk = q % BBLK;
+            const int src = pl < 4 ? pl : (pl == 4 ? 2 : pl == 5 ? 3 : pl == 6 ? 0 : 1);
+            const float* ub = (pl < 4 ? Bf : Bg) + src * pb + (size_t)(k0 + blk * RB) * a.ldb + n0;
+            dma16(ub + b_lane_off, &sm.B[b][pl][blk][0]);
+        }
+    };
+    auto chunk_inside = [&](int c) { return !edge_tile && (c * KT + KT <= a.n); };
+
     const int wm = wave & 1, wn = wave >> 1;
     const int lr = lane & 31, lg = lane >> 5;
 
@@ -240,12 +280,49 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
         }
     };
 
+    // MODE 1 fragments: raw split words, zeroed where masked, D/E signs by
+    // flipping the sign bits of hi and lo
+    auto load_b_words = [&](int b, int nb, int c, bool mask, unsigned (&w)[8][8]) {
+        const int cl = wn * (NT / 2) + nb * 32 + lr;
+        const bool col_ok = !mask || (n0 + cl < a.s);
+#pragma unroll
+        for (int pl = 0; pl < 8; ++pl) {
+            const unsigned flip = (pl == 4 || pl == 7) ? 0x80008000u : 0u;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = 8 * lg + j;
+                const unsigned v = __builtin_bit_cast(unsigned, sm.B[b][pl][k / RB][(k % RB) * NT + cl]);
+                const bool ok = col_ok && (!mask || (c * KT + k < a.n));
+                w[pl][j] = ok ? (v ^ flip) : 0u;
+            }
+        }
+    };
+    auto load_a_words = [&](int b, int mb, int c, bool mask, unsigned (&w)[4][8]) {
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        const int rl = wm * (MT / 2) + mb * 32 + lr;
+        const int blk = rl >> 4, i = rl & 15;
+        const int s0 = 4 * i + ((2 * lg) ^ ((i >> 2) & 3));
+        const int s1 = 4 * i + ((2 * lg + 1) ^ ((i >> 2) & 3));
+        const bool row_ok = !mask || (m0 + rl < a.m);
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) {
+            const u4 u = *reinterpret_cast<const u4*>(&sm.A[b][pl][blk][4 * s0]);
+            const u4 v = *reinterpret_cast<const u4*>(&sm.A[b][pl][blk][4 * s1]);
+            const unsigned x[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const bool ok = row_ok && (!mask || (c * KT + 8 * lg + j < a.n));
+                w[pl][j] = ok ? x[j] : 0u;
+            }
+        }
+    };
+
     auto compute = [&](int c, int b, bool mask) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            float xb[8][8];
-            load_b(b, nb, c, mask, xb);
             if constexpr (MODE == 0) {
+                float xb[8][8];
+                load_b(b, nb, c, mask, xb);
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb) {
                     float xa[4][8];
@@ -277,15 +354,31 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                 }
             } else {
                 V8 bh[8], bl[8];
+                if constexpr (MODE == 1) {
+                    unsigned wb[8][8];
+                    load_b_words(b, nb, c, mask, wb);
 #pragma unroll
-                for (int pl = 0; pl < 8; ++pl) split8<H>(xb[pl], bh[pl], bl[pl]);
+                    for (int pl = 0; pl < 8; ++pl) unpack8(wb[pl], bh[pl], bl[pl]);
+                } else {
+                    float xb[8][8];
+                    load_b(b, nb, c, mask, xb);
+#pragma unroll
+                    for (int pl = 0; pl < 8; ++pl) split8<H>(xb[pl], bh[pl], bl[pl]);
+                }
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb) {
-                    float xa[4][8];
-                    load_a(b, mb, c, mask, xa);
                     V8 ah[4], al[4];
+                    if constexpr (MODE == 1) {
+                        unsigned wa[4][8];
+                        load_a_words(b, mb, c, mask, wa);
 #pragma unroll
-                    for (int pl = 0; pl < 4; ++pl) split8<H>(xa[pl], ah[pl], al[pl]);
+                        for (int pl = 0; pl < 4; ++pl) unpack8(wa[pl], ah[pl], al[pl]);
+                    } else {
+                        float xa[4][8];
+                        load_a(b, mb, c, mask, xa);
+#pragma unroll
+                        for (int pl = 0; pl < 4; ++pl) split8<H>(xa[pl], ah[pl], al[pl]);
+                    }
                     const V8 nh1 = neg8(ah[1]), nl1 = neg8(al[1]);
                     const V8 nh3 = neg8(ah[3]), nl3 = neg8(al[3]);
                     v16f c0 = acc[0][mb][nb], c1 = acc[1][mb][nb], c2 = acc[2][mb][nb], c3 = acc[3][mb][nb];
@@ -308,11 +401,15 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
         }
     };
 
-    issue(0, 0);
+    if (chunk_inside(0)) issue_fast(0, 0);
+    else issue(0, 0);
     for (int c = 0; c < nchunks; ++c) {
         __builtin_amdgcn_s_waitcnt(0);       // this wave's DMA of chunk c has landed
         __syncthreads();                     // ... and every wave's; chunk c - 1 is consumed
-        if (c + 1 < nchunks) issue(c + 1, (c + 1) & 1);
+        if (c + 1 < nchunks) {
+            if (chunk_inside(c + 1)) issue_fast(c + 1, (c + 1) & 1);
+            else issue(c + 1, (c + 1) & 1);
+        }
         const bool mask = edge_tile || (c * KT + KT > a.n);
         if (mask) compute(c, c & 1, true);
         else compute(c, c & 1, false);

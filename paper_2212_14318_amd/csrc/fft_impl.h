@@ -142,6 +142,15 @@ struct FftJobs2 {
     FftJob<T> j[2];
 };
 
+// bf16 split of one real in one word: low half hi = rn(x), high half
+// lo = rn(x - hi), both round-to-nearest-even (hardware conversion).
+__device__ __forceinline__ unsigned split_bf16_word(float x) {
+    const __bf16 hi = (__bf16)x;
+    const __bf16 lo = (__bf16)(x - (float)hi);
+    return (unsigned)__builtin_bit_cast(unsigned short, hi) |
+           ((unsigned)__builtin_bit_cast(unsigned short, lo) << 16);
+}
+
 // Transform one complex tube: part 0 = X1 (planes 0, 1), part 1 = X2
 // (planes 2, 3) at flattened position e = i * cols + c of job jb.
 template <int P, bool INV, typename T, int POL = 0>
@@ -161,6 +170,18 @@ __device__ __forceinline__ void tube_fft_one(const FftJob<T>& jb, int part, long
 #pragma unroll
     for (int k = 0; k < P; ++k) x[k] = V{sre[k * sface], sim[k * sface]};
     Dft<P, P, INV, V, POL>::run(x, tw);
+    if constexpr (!INV && sizeof(T) == 4) {
+        if (jb.pack) {   // bf16 split of every real: hi | lo << 16
+            unsigned* ure = reinterpret_cast<unsigned*>(dre);
+            unsigned* uim = reinterpret_cast<unsigned*>(dim);
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                ure[k * dface] = split_bf16_word(x[k].x);
+                uim[k * dface] = split_bf16_word(x[k].y);
+            }
+            return;
+        }
+    }
     const T scale = INV ? T(1) / T(P) : T(1);
 #pragma unroll
     for (int k = 0; k < P; ++k) {

@@ -18,11 +18,15 @@ inline size_t plane_elems(long p, long rows, long ld) { return (size_t)p * (size
 // with row stride src_ld and written to `dst` with row stride dst_ld.  Both
 // buffers are [4][p][rows][ld].  Planes (0,1) form the complex part X1,
 // planes (2,3) the part X2 of the Cayley-Dickson form.
+// pack = 1 (float forward transforms only): every output real x is stored as
+// the 32-bit word hi | lo << 16 of its bf16 split, hi = rn(x), lo = rn(x - hi)
+// -- the operand format of the split-bf16 facewise products.
 template <typename T>
 struct FftJob {
     const T* src;
     T* dst;
     int rows, cols, src_ld, dst_ld;
+    int pack;
 };
 
 // Twiddle tables of one p: tw[k] = exp(-2 pi i k / p), k in [0, p), made in

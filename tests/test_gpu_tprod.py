@@ -42,6 +42,30 @@ def test_tube_fft_matches_numpy(p):
     assert rel_err(back, X) < 2e-6
 
 
+def _unpack_split_words(t):
+    """(hi | lo << 16) bf16 words -> hi + lo as float64."""
+    w = t.contiguous().view(torch.int32).cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    hi = ((w & 0xFFFF) << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+    lo = ((w >> 16) << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+    return hi, lo
+
+
+@pytest.mark.parametrize("p", [1, 7, 32, 64])
+def test_tube_fft_split_words(p):
+    """Forward transform in the split-bf16 operand format: each word holds
+    hi = rn_bf16(x) and lo = rn_bf16(x - hi); hi + lo keeps ~16 bits."""
+    rows, cols = 9, 33
+    X = synth.quat_tensor(rows, cols, p, seed=150 + p)
+    H = tube_fft(to_dev(X), precision="split_bf16")
+    hi, lo = _unpack_split_words(H)
+    w1 = np.fft.fft(X[0] + 1j * X[1], axis=0)
+    w2 = np.fft.fft(X[2] + 1j * X[3], axis=0)
+    want = np.stack([w1.real, w1.imag, w2.real, w2.imag])
+    assert rel_err(hi + lo, want) < 2e-5
+    assert rel_err(hi, want) < 1e-2          # hi alone is only a bf16 rounding
+    assert np.all(np.abs(lo) <= np.abs(hi) * 2.0 ** -8 + 1e-30)
+
+
 @pytest.mark.parametrize("p", [1, 3, 8, 16, 30, 64])
 def test_tube_fft_fp64(p):
     X = synth.quat_tensor(5, 9, p, seed=200 + p)
