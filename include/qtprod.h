@@ -78,10 +78,11 @@ typedef enum {
     QT_FP64 = 3         /* every step in double (small problems, validation) */
 } qt_precision;
 
-/* Largest p accepted by the argument checks.  The lengths with a kernel in
- * this build are the 7-smooth p (prime factors 2, 3, 5, 7) up to 128 for the
- * float precisions and up to 64 for QT_FP64 (64 in the batched path); other
- * p return QT_ERR_UNSUPPORTED. */
+/* Largest p served.  Every p in [1, QT_MAX_P] is supported by the single-
+ * problem entry points: 7-smooth p (prime factors 2, 3, 5, 7) up to 128 (64
+ * for QT_FP64) have register-resident tube FFTs, every other p goes through
+ * Bluestein's algorithm (chirp tables in FP64 on the device).  The batched
+ * path serves 7-smooth p <= 64. */
 #define QT_MAX_P 4096
 
 /* Library ABI version (major * 100 + minor). */

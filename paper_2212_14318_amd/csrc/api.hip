@@ -47,10 +47,11 @@ size_t fourier_bytes(long rows, long cols, long p, int prec) {
     return align_up(4 * (size_t)p * (size_t)rows * (size_t)qt::fourier_ld(cols) * real_bytes(prec));
 }
 
+// Every p up to QT_MAX_P: register-resident kernels for the 7-smooth lengths
+// they cover, Bluestein for all others.
 bool p_supported(int p, int prec) {
-    if (p < 1 || p > QT_MAX_P) return false;
-
-    return prec == QT_FP64 ? qt::tube_fft_supported<double>(p) : qt::tube_fft_supported<float>(p);
+    (void)prec;
+    return p >= 1 && p <= QT_MAX_P;
 }
 
 // ------------------------------------------------------------- plan cache
@@ -77,15 +78,40 @@ int get_twiddles(int p, hipStream_t stream, Twiddles* out) {
         *out = it->second;
         return QT_OK;
     }
-    Twiddles tw{nullptr, nullptr};
+    Twiddles tw{};
     if (hipMalloc((void**)&tw.f32, sizeof(float2) * (size_t)p) != hipSuccess) return QT_ERR_ALLOC;
     if (hipMalloc((void**)&tw.f64, sizeof(double2) * (size_t)p) != hipSuccess) {
         (void)hipFree(tw.f32);
         return QT_ERR_ALLOC;
     }
-    if (qt::launch_twiddles(p, tw, stream) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) {
+    bool ok = qt::launch_twiddles(p, tw, stream) == hipSuccess;
+    if (ok && !qt::tube_fft_supported<double>(p)) {
+        // Bluestein tables in one allocation: 4 x 16 B and 4 x 8 B per entry
+        qt::BluesteinTables& bt = tw.blue;
+        bt.M = qt::bluestein_length(p);
+        const size_t n64 = 2 * (size_t)bt.M + (size_t)p + (size_t)bt.M / 2;
+        char* mem = nullptr;
+        if (hipMalloc((void**)&mem, n64 * (sizeof(double2) + sizeof(float2))) != hipSuccess) {
+            (void)hipFree(tw.f32);
+            (void)hipFree(tw.f64);
+            return QT_ERR_ALLOC;
+        }
+        double2* d = reinterpret_cast<double2*>(mem);
+        bt.chirp64 = d; d += p;
+        bt.hat_fwd64 = d; d += bt.M;
+        bt.hat_inv64 = d; d += bt.M;
+        bt.twm64 = d; d += bt.M / 2;
+        float2* s32 = reinterpret_cast<float2*>(d);
+        bt.chirp32 = s32; s32 += p;
+        bt.hat_fwd32 = s32; s32 += bt.M;
+        bt.hat_inv32 = s32; s32 += bt.M;
+        bt.twm32 = s32;
+        ok = qt::launch_bluestein_tables(p, bt, stream) == hipSuccess;
+    }
+    if (!ok || hipStreamSynchronize(stream) != hipSuccess) {
         (void)hipFree(tw.f32);
         (void)hipFree(tw.f64);
+        if (tw.blue.M) (void)hipFree(tw.blue.chirp64);
         return QT_ERR_HIP;
     }
     g_plans.emplace(PlanKey{dev, p}, tw);

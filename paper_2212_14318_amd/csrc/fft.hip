@@ -45,6 +45,10 @@ template <>
 hipError_t launch_tube_fft<float>(int p, bool inverse, const FftJob<float>* jobs, int njobs,
                                   const Twiddles& tw, hipStream_t stream) {
     if (njobs < 1 || njobs > 2) return hipErrorInvalidValue;
+    if (!tube_fft_supported<float>(p)) {
+        if (tw.blue.M == 0) return hipErrorNotSupported;
+        return launch_bluestein<float>(p, inverse, jobs, njobs, tw.blue, stream);
+    }
     switch (p) {
 #define QT_CASE(P)                                                                           \
     case P:                                                                                  \
@@ -60,6 +64,10 @@ template <>
 hipError_t launch_tube_fft<double>(int p, bool inverse, const FftJob<double>* jobs, int njobs,
                                    const Twiddles& tw, hipStream_t stream) {
     if (njobs < 1 || njobs > 2) return hipErrorInvalidValue;
+    if (!tube_fft_supported<double>(p)) {
+        if (tw.blue.M == 0) return hipErrorNotSupported;
+        return launch_bluestein<double>(p, inverse, jobs, njobs, tw.blue, stream);
+    }
     switch (p) {
 #define QT_CASE(P)                                                                           \
     case P:                                                                                  \

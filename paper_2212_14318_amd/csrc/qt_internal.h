@@ -29,12 +29,31 @@ struct FftJob {
     int pack;
 };
 
+// Bluestein tables of one p (lengths without a register-resident kernel):
+// M = smallest power of two >= 2p - 1; chirp c_k = exp(i pi (k^2 mod 2p) / p)
+// (k < p); hat_fwd / hat_inv = length-M DFTs of the chirp sequence and of its
+// conjugate; twm = exp(-2 pi i j / M), j < M/2.  All made in FP64 on the
+// device, stored in both precisions.  M = 0 when p does not need them.
+struct BluesteinTables {
+    int M;
+    double2 *chirp64, *hat_fwd64, *hat_inv64, *twm64;
+    float2 *chirp32, *hat_fwd32, *hat_inv32, *twm32;
+};
+
 // Twiddle tables of one p: tw[k] = exp(-2 pi i k / p), k in [0, p), made in
-// FP64 on the device and stored in both precisions.
+// FP64 on the device and stored in both precisions, plus the Bluestein tables
+// when some precision has no register-resident kernel for p.
 struct Twiddles {
     float2* f32;
     double2* f64;
+    BluesteinTables blue;
 };
+
+int bluestein_length(int p);
+hipError_t launch_bluestein_tables(int p, const BluesteinTables& bt, hipStream_t stream);
+template <typename T>
+hipError_t launch_bluestein(int p, bool inverse, const FftJob<T>* jobs, int njobs,
+                            const BluesteinTables& bt, hipStream_t stream);
 
 // Forward (inverse = false) or inverse (inverse = true, with the 1/p scale)
 // tube FFT of up to two jobs in one launch.  Returns hipSuccess or the launch
