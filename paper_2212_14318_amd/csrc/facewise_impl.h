@@ -170,7 +170,8 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     constexpr int MB = MT / 64, NB = NT / 64;
     constexpr int ABLK = MT / 16, BBLK = NT / 16;       // 1 KB blocks per plane
     constexpr int RB = 256 / NT, CQ = NT / 4;           // B block: RB k-rows of CQ 16-byte pieces
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform (SGPR)
     const int g = (a.p - f) % a.p;
     const size_t pa = (size_t)a.p * a.m * a.lda;
     const size_t pb = (size_t)a.p * a.n * a.ldb;
@@ -184,8 +185,8 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     auto issue = [&](int c, int b) {
         const int k0 = c * KT;
 #pragma unroll
-        for (int q = wave; q < 4 * ABLK; q += 4) {
-            const int pl = q / ABLK, blk = q % ABLK;
+        for (int qq = 0; qq < ABLK; ++qq) {
+            const int q = 4 * qq + wave, pl = q / ABLK, blk = q % ABLK;
             const int i = lane >> 2;
             const int kq = (lane & 3) ^ ((i >> 2) & 3);
             int grow = m0 + blk * 16 + i;
@@ -195,8 +196,8 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
             dma16(Af + pl * pa + (size_t)grow * a.lda + gk, &sm.A[b][pl][blk][0]);
         }
 #pragma unroll
-        for (int q = wave; q < 8 * BBLK; q += 4) {
-            const int pl = q / BBLK, blk = q % BBLK;
+        for (int qq = 0; qq < 2 * BBLK; ++qq) {
+            const int q = 4 * qq + wave, pl = q / BBLK, blk = q % BBLK;
             // staged planes: 0..3 = B^[f] (B1r, B1i, B2r, B2i); 4..7 = D, E from
             // B^[g]: Dr = -B2r, Di = B2i, Er = B1r, Ei = -B1i (signs applied later)
             const int src = pl < 4 ? pl : (pl == 4 ? 2 : pl == 5 ? 3 : pl == 6 ? 0 : 1);
@@ -217,14 +218,14 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     auto issue_fast = [&](int c, int b) {
         const int k0 = c * KT;
 #pragma unroll
-        for (int q = wave; q < 4 * ABLK; q += 4) {
-            const int pl = q / ABLK, blk = q % ABLK;
+        for (int qq = 0; qq < ABLK; ++qq) {
+            const int q = 4 * qq + wave, pl = q / ABLK, blk = q % ABLK;
             const float* ub = Af + pl * pa + (size_t)(m0 + blk * 16) * a.lda + k0;
             dma16(ub + a_lane_off, &sm.A[b][pl][blk][0]);
         }
 #pragma unroll
-        for (int q = wave; q < 8 * BBLK; q += 4) {
-            const int pl = q / BBLK, blk = q % BBLK;
+        for (int qq = 0; qq < 2 * BBLK; ++qq) {
+            const int q = 4 * qq + wave, pl = q / BBLK, blk = q % BBLK;
             const int src = pl < 4 ? pl : (pl == 4 ? 2 : pl == 5 ? 3 : pl == 6 ? 0 : 1);
             const float* ub = (pl < 4 ? Bf : Bg) + src * pb + (size_t)(k0 + blk * RB) * a.ldb + n0;
             dma16(ub + b_lane_off, &sm.B[b][pl][blk][0]);
@@ -246,21 +247,6 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                 for (int r = 0; r < 16; ++r) acc[c][mb][nb][r] = 0.f;
 
     // ---- fragments of chunk c from buffer b; MASK zeroes out-of-range entries
-    auto load_b = [&](int b, int nb, int c, bool mask, float (&x)[8][8]) {
-        const int cl = wn * (NT / 2) + nb * 32 + lr;
-        const bool col_ok = !mask || (n0 + cl < a.s);
-#pragma unroll
-        for (int pl = 0; pl < 8; ++pl) {
-            const float sgn = (pl == 4 || pl == 7) ? -(MODE == 2 ? sb : 1.f) : (MODE == 2 ? sb : 1.f);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = 8 * lg + j;
-                const float v = sm.B[b][pl][k / RB][(k % RB) * NT + cl];
-                const bool ok = col_ok && (!mask || (c * KT + k < a.n));
-                x[pl][j] = ok ? v * sgn : 0.f;
-            }
-        }
-    };
     auto load_a = [&](int b, int mb, int c, bool mask, float (&x)[4][8]) {
         const int rl = wm * (MT / 2) + mb * 32 + lr;
         const int blk = rl >> 4, i = rl & 15;
@@ -280,23 +266,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
         }
     };
 
-    // MODE 1 fragments: raw split words, zeroed where masked, D/E signs by
-    // flipping the sign bits of hi and lo
-    auto load_b_words = [&](int b, int nb, int c, bool mask, unsigned (&w)[8][8]) {
-        const int cl = wn * (NT / 2) + nb * 32 + lr;
-        const bool col_ok = !mask || (n0 + cl < a.s);
-#pragma unroll
-        for (int pl = 0; pl < 8; ++pl) {
-            const unsigned flip = (pl == 4 || pl == 7) ? 0x80008000u : 0u;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = 8 * lg + j;
-                const unsigned v = __builtin_bit_cast(unsigned, sm.B[b][pl][k / RB][(k % RB) * NT + cl]);
-                const bool ok = col_ok && (!mask || (c * KT + k < a.n));
-                w[pl][j] = ok ? (v ^ flip) : 0u;
-            }
-        }
-    };
+    // MODE 1 A fragments: raw split words, zeroed where masked
     auto load_a_words = [&](int b, int mb, int c, bool mask, unsigned (&w)[4][8]) {
         typedef unsigned u4 __attribute__((ext_vector_type(4)));
         const int rl = wm * (MT / 2) + mb * 32 + lr;
@@ -317,102 +287,153 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
         }
     };
 
+    // One chunk, B plane by B plane: the A fragments of the chunk stay live,
+    // each B plane is loaded, (split,) negated where a term needs -Im A, and
+    // used at once by the two terms that contain it, on both M blocks:
+    //   plane 0 B1r: ReC1 += Ar1 B1r   ImC1 += Ai1 B1r
+    //   plane 1 B1i: ReC1 -= Ai1 B1i   ImC1 += Ar1 B1i
+    //   plane 2 B2r: ReC2 += Ar1 B2r   ImC2 += Ai1 B2r
+    //   plane 3 B2i: ReC2 -= Ai1 B2i   ImC2 += Ar1 B2i
+    //   plane 4 Dr : ReC1 += Ar2 Dr    ImC1 += Ai2 Dr
+    //   plane 5 Di : ReC1 -= Ai2 Di    ImC1 += Ar2 Di
+    //   plane 6 Er : ReC2 += Ar2 Er    ImC2 += Ai2 Er
+    //   plane 7 Ei : ReC2 -= Ai2 Ei    ImC2 += Ar2 Ei
+    // i.e. plane q feeds accumulators (q & 2 ? C2 : C1), real part from
+    // A-plane (q & 1 ? Im : Re) and imaginary part from the other one.
     auto compute = [&](int c, int b, bool mask) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
+            const int cl = wn * (NT / 2) + nb * 32 + lr;
+            const bool col_ok = !mask || (n0 + cl < a.s);
             if constexpr (MODE == 0) {
-                float xb[8][8];
-                load_b(b, nb, c, mask, xb);
+                float xa[MB][4][8];
 #pragma unroll
-                for (int mb = 0; mb < MB; ++mb) {
-                    float xa[4][8];
-                    load_a(b, mb, c, mask, xa);
-                    v16f c0 = acc[0][mb][nb], c1 = acc[1][mb][nb], c2 = acc[2][mb][nb], c3 = acc[3][mb][nb];
+                for (int mb = 0; mb < MB; ++mb) load_a(b, mb, c, mask, xa[mb]);
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) {
-                        const float ar1 = xa[0][t], ai1 = xa[1][t], ar2 = xa[2][t], ai2 = xa[3][t];
-                        // Re C1 = Ar1 B1r - Ai1 B1i + Ar2 Dr - Ai2 Di ; Im C1 = Ar1 B1i + Ai1 B1r + Ar2 Di + Ai2 Dr
-                        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar1, xb[0][t], c0, 0, 0, 0);
-                        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai1, xb[1][t], c0, 0, 0, 0);
-                        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar2, xb[4][t], c0, 0, 0, 0);
-                        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai2, xb[5][t], c0, 0, 0, 0);
-                        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar1, xb[1][t], c1, 0, 0, 0);
-                        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai1, xb[0][t], c1, 0, 0, 0);
-                        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar2, xb[5][t], c1, 0, 0, 0);
-                        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai2, xb[4][t], c1, 0, 0, 0);
-                        // Re C2 = Ar1 B2r - Ai1 B2i + Ar2 Er - Ai2 Ei ; Im C2 = Ar1 B2i + Ai1 B2r + Ar2 Ei + Ai2 Er
-                        c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar1, xb[2][t], c2, 0, 0, 0);
-                        c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai1, xb[3][t], c2, 0, 0, 0);
-                        c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar2, xb[6][t], c2, 0, 0, 0);
-                        c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai2, xb[7][t], c2, 0, 0, 0);
-                        c3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar1, xb[3][t], c3, 0, 0, 0);
-                        c3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai1, xb[2][t], c3, 0, 0, 0);
-                        c3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar2, xb[7][t], c3, 0, 0, 0);
-                        c3 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai2, xb[6][t], c3, 0, 0, 0);
+                for (int q = 0; q < 8; ++q) {
+                    const float sgn = (q == 4 || q == 7) ? -1.f : 1.f;
+                    float y[8], ny[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const int k = 8 * lg + j;
+                        const float v = sm.B[b][q][k / RB][(k % RB) * NT + cl];
+                        const bool ok = col_ok && (!mask || (c * KT + k < a.n));
+                        y[j] = ok ? v * sgn : 0.f;
+                        ny[j] = -y[j];
                     }
-                    acc[0][mb][nb] = c0; acc[1][mb][nb] = c1; acc[2][mb][nb] = c2; acc[3][mb][nb] = c3;
+                    const int cre = (q & 2) ? 2 : 0;          // ReC1 / ReC2
+                    const int apl = (q & 4) ? 2 : 0;          // A1 / A2 real plane
+#pragma unroll
+                    for (int t = 0; t < 8; ++t)
+#pragma unroll
+                        for (int mb = 0; mb < MB; ++mb) {
+                            const float ar = xa[mb][apl][t], ai = xa[mb][apl + 1][t];
+                            if ((q & 1) == 0) {   // real B part: Re += Ar Y, Im += Ai Y
+                                acc[cre][mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, y[t], acc[cre][mb][nb], 0, 0, 0);
+                                acc[cre + 1][mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, y[t], acc[cre + 1][mb][nb], 0, 0, 0);
+                            } else {              // imaginary B part: Re -= Ai Y, Im += Ar Y
+                                acc[cre][mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, ny[t], acc[cre][mb][nb], 0, 0, 0);
+                                acc[cre + 1][mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, y[t], acc[cre + 1][mb][nb], 0, 0, 0);
+                            }
+                        }
                 }
             } else {
-                V8 bh[8], bl[8];
-                if constexpr (MODE == 1) {
-                    unsigned wb[8][8];
-                    load_b_words(b, nb, c, mask, wb);
-#pragma unroll
-                    for (int pl = 0; pl < 8; ++pl) unpack8(wb[pl], bh[pl], bl[pl]);
-                } else {
-                    float xb[8][8];
-                    load_b(b, nb, c, mask, xb);
-#pragma unroll
-                    for (int pl = 0; pl < 8; ++pl) split8<H>(xb[pl], bh[pl], bl[pl]);
-                }
+                V8 ah[MB][4], al[MB][4];
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb) {
-                    V8 ah[4], al[4];
                     if constexpr (MODE == 1) {
                         unsigned wa[4][8];
                         load_a_words(b, mb, c, mask, wa);
 #pragma unroll
-                        for (int pl = 0; pl < 4; ++pl) unpack8(wa[pl], ah[pl], al[pl]);
+                        for (int pl = 0; pl < 4; ++pl) unpack8(wa[pl], ah[mb][pl], al[mb][pl]);
                     } else {
                         float xa[4][8];
                         load_a(b, mb, c, mask, xa);
 #pragma unroll
-                        for (int pl = 0; pl < 4; ++pl) split8<H>(xa[pl], ah[pl], al[pl]);
+                        for (int pl = 0; pl < 4; ++pl) split8<H>(xa[pl], ah[mb][pl], al[mb][pl]);
                     }
-                    const V8 nh1 = neg8(ah[1]), nl1 = neg8(al[1]);
-                    const V8 nh3 = neg8(ah[3]), nl3 = neg8(al[3]);
-                    v16f c0 = acc[0][mb][nb], c1 = acc[1][mb][nb], c2 = acc[2][mb][nb], c3 = acc[3][mb][nb];
-#define QT_SPLIT3(ACC, XH, XL, YI)                      \
-    ACC = mfma16<H>(XL, bh[YI], ACC);                   \
-    ACC = mfma16<H>(XH, bl[YI], ACC);                   \
-    ACC = mfma16<H>(XH, bh[YI], ACC);
-                    QT_SPLIT3(c0, ah[0], al[0], 0) QT_SPLIT3(c0, nh1, nl1, 1)
-                    QT_SPLIT3(c0, ah[2], al[2], 4) QT_SPLIT3(c0, nh3, nl3, 5)
-                    QT_SPLIT3(c1, ah[0], al[0], 1) QT_SPLIT3(c1, ah[1], al[1], 0)
-                    QT_SPLIT3(c1, ah[2], al[2], 5) QT_SPLIT3(c1, ah[3], al[3], 4)
-                    QT_SPLIT3(c2, ah[0], al[0], 2) QT_SPLIT3(c2, nh1, nl1, 3)
-                    QT_SPLIT3(c2, ah[2], al[2], 6) QT_SPLIT3(c2, nh3, nl3, 7)
-                    QT_SPLIT3(c3, ah[0], al[0], 3) QT_SPLIT3(c3, ah[1], al[1], 2)
-                    QT_SPLIT3(c3, ah[2], al[2], 7) QT_SPLIT3(c3, ah[3], al[3], 6)
-#undef QT_SPLIT3
-                    acc[0][mb][nb] = c0; acc[1][mb][nb] = c1; acc[2][mb][nb] = c2; acc[3][mb][nb] = c3;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    V8 yh, yl;
+                    if constexpr (MODE == 1) {
+                        const unsigned flip = (q == 4 || q == 7) ? 0x80008000u : 0u;
+                        unsigned w[8];
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            const int k = 8 * lg + j;
+                            const unsigned v = __builtin_bit_cast(unsigned, sm.B[b][q][k / RB][(k % RB) * NT + cl]);
+                            const bool ok = col_ok && (!mask || (c * KT + k < a.n));
+                            w[j] = ok ? (v ^ flip) : 0u;
+                        }
+                        unpack8(w, yh, yl);
+                    } else {
+                        const float sgn = (q == 4 || q == 7) ? -sb : sb;
+                        float x[8];
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            const int k = 8 * lg + j;
+                            const float v = sm.B[b][q][k / RB][(k % RB) * NT + cl];
+                            const bool ok = col_ok && (!mask || (c * KT + k < a.n));
+                            x[j] = ok ? v * sgn : 0.f;
+                        }
+                        split8<H>(x, yh, yl);
+                    }
+                    const int cre = (q & 2) ? 2 : 0;
+                    const int apl = (q & 4) ? 2 : 0;
+                    if ((q & 1) == 0) {
+#pragma unroll
+                        for (int mb = 0; mb < MB; ++mb) {
+                            v16f r = acc[cre][mb][nb], i = acc[cre + 1][mb][nb];
+                            r = mfma16<H>(al[mb][apl], yh, r);
+                            i = mfma16<H>(al[mb][apl + 1], yh, i);
+                            r = mfma16<H>(ah[mb][apl], yl, r);
+                            i = mfma16<H>(ah[mb][apl + 1], yl, i);
+                            r = mfma16<H>(ah[mb][apl], yh, r);
+                            i = mfma16<H>(ah[mb][apl + 1], yh, i);
+                            acc[cre][mb][nb] = r;
+                            acc[cre + 1][mb][nb] = i;
+                        }
+                    } else {
+                        const V8 nyh = neg8(yh), nyl = neg8(yl);
+#pragma unroll
+                        for (int mb = 0; mb < MB; ++mb) {
+                            v16f r = acc[cre][mb][nb], i = acc[cre + 1][mb][nb];
+                            r = mfma16<H>(al[mb][apl + 1], nyh, r);
+                            i = mfma16<H>(al[mb][apl], yh, i);
+                            r = mfma16<H>(ah[mb][apl + 1], nyl, r);
+                            i = mfma16<H>(ah[mb][apl], yl, i);
+                            r = mfma16<H>(ah[mb][apl + 1], nyh, r);
+                            i = mfma16<H>(ah[mb][apl], yh, i);
+                            acc[cre][mb][nb] = r;
+                            acc[cre + 1][mb][nb] = i;
+                        }
+                    }
                 }
             }
         }
     };
 
-    if (chunk_inside(0)) issue_fast(0, 0);
-    else issue(0, 0);
-    for (int c = 0; c < nchunks; ++c) {
+    auto advance = [&](int c) {
         __builtin_amdgcn_s_waitcnt(0);       // this wave's DMA of chunk c has landed
         __syncthreads();                     // ... and every wave's; chunk c - 1 is consumed
         if (c + 1 < nchunks) {
             if (chunk_inside(c + 1)) issue_fast(c + 1, (c + 1) & 1);
             else issue(c + 1, (c + 1) & 1);
         }
-        const bool mask = edge_tile || (c * KT + KT > a.n);
-        if (mask) compute(c, c & 1, true);
-        else compute(c, c & 1, false);
+    };
+    if (chunk_inside(0)) issue_fast(0, 0);
+    else issue(0, 0);
+    // Two loops, each with a single compute variant, so that the accumulators
+    // are defined in one place per loop and stay in AGPRs across iterations.
+    const int nfull = edge_tile ? 0 : a.n / KT;
+    for (int c = 0; c < nfull; ++c) {
+        advance(c);
+        compute(c, c & 1, false);
+    }
+    for (int c = nfull; c < nchunks; ++c) {
+        advance(c);
+        compute(c, c & 1, true);
     }
     __syncthreads();                         // LDS may be reused by the next tile
     store_tile<MB, NB>(a, f, m0 + wm * (MT / 2), n0 + wn * (NT / 2), acc,
