@@ -20,36 +20,55 @@
 // facewise_impl.h, shared with the persistent batched kernel.
 #include "facewise_impl.h"
 
+
 namespace qt {
 namespace {
 
 using namespace detail;
 
+// Waves per workgroup of a tile shape: the 128 x 64 tile runs 8 waves (4 x 2,
+// each 32 x 32), so two waves share a SIMD and hide each other's LDS and
+// VALU latency; the 64-wide tiles run 4 waves (2 x 2).
+__host__ __device__ constexpr int tile_waves(int cfg) { return cfg == TILE_128x64 ? 8 : 4; }
+
+// Workgroup -> (frequency, tile row, tile column) over a 1-D grid.
+struct TileGrid {
+    int tiles_m, tiles_n, p;
+};
+
+__device__ __forceinline__ bool tile_of_block(const TileGrid& t, int& f, int& tm, int& tn) {
+    const int L = blockIdx.x;
+    const int per = t.tiles_m * t.tiles_n;
+    f = L / per;
+    tm = (L - f * per) / t.tiles_n;
+    tn = L - f * per - tm * t.tiles_n;
+    return f < t.p;
+}
+
 template <int CFG>
-__global__ void __launch_bounds__(256)
-facewise_f32_kernel(FacewiseArgs<float> a, int tiles_n) {
+__global__ void __launch_bounds__(64 * tile_waves(CFG))
+facewise_f32_kernel(FacewiseArgs<float> a, TileGrid tg) {
     constexpr int MT = tile_mt(CFG), NT = tile_nt(CFG);
     __shared__ __attribute__((aligned(16))) V2Smem<MT, NT> sm;
-    const int tm = blockIdx.x / tiles_n;
-    const int tn = blockIdx.x - tm * tiles_n;
-    tile_v2<0, MT, NT>(a, blockIdx.y, tm * MT, tn * NT, 1.f, 1.f, sm);
+    int f, tm, tn;
+    if (!tile_of_block(tg, f, tm, tn)) return;
+    tile_v2<0, MT, NT, tile_waves(CFG)>(a, f, tm * MT, tn * NT, 1.f, 1.f, sm);
 }
 
 template <typename H, int CFG>
-__global__ void __launch_bounds__(256)
-facewise_split_kernel(FacewiseArgs<float> a, int tiles_n, const float* __restrict__ scales) {
+__global__ void __launch_bounds__(64 * tile_waves(CFG))
+facewise_split_kernel(FacewiseArgs<float> a, TileGrid tg, const float* __restrict__ scales) {
     constexpr int MT = tile_mt(CFG), NT = tile_nt(CFG);
     constexpr int MODE = std::is_same<H, _Float16>::value ? 2 : 1;
     __shared__ __attribute__((aligned(16))) V2Smem<MT, NT> sm;
-    const int f = blockIdx.y;
-    const int tm = blockIdx.x / tiles_n;
-    const int tn = blockIdx.x - tm * tiles_n;
+    int f, tm, tn;
+    if (!tile_of_block(tg, f, tm, tn)) return;
     float sa = 1.f, sb = 1.f;
     if (scales) {   // fp16: scales[f] for A^ at f, scales[p + f] for the B^ pair {f, -f}
         sa = scales[f];
         sb = scales[a.p + f];
     }
-    tile_v2<MODE, MT, NT>(a, f, tm * MT, tn * NT, sa, sb, sm);
+    tile_v2<MODE, MT, NT, tile_waves(CFG)>(a, f, tm * MT, tn * NT, sa, sb, sm);
 }
 
 // ---------------------------------------------------------------- FP64 VALU
@@ -182,16 +201,17 @@ static hipError_t launch_cfg(const FacewiseArgs<float>& a, int precision, const 
     constexpr int MT = tile_mt(CFG), NT = tile_nt(CFG);
     const int tiles_m = (a.m + MT - 1) / MT;
     const int tiles_n = (a.s + NT - 1) / NT;
-    const dim3 grid(tiles_m * tiles_n, a.p);
+    const TileGrid tg{tiles_m, tiles_n, a.p};
+    const dim3 grid((unsigned)(tiles_m * tiles_n * a.p)), block(64 * tile_waves(CFG));
     if (precision == 0) {
-        hipLaunchKernelGGL((facewise_f32_kernel<CFG>), grid, dim3(256), 0, stream, a, tiles_n);
+        hipLaunchKernelGGL((facewise_f32_kernel<CFG>), grid, block, 0, stream, a, tg);
     } else if (precision == 1) {
-        hipLaunchKernelGGL((facewise_split_kernel<__bf16, CFG>), grid, dim3(256), 0, stream, a,
-                           tiles_n, (const float*)nullptr);
+        hipLaunchKernelGGL((facewise_split_kernel<__bf16, CFG>), grid, block, 0, stream, a,
+                           tg, (const float*)nullptr);
     } else if (precision == 2) {
         if (!scales) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((facewise_split_kernel<_Float16, CFG>), grid, dim3(256), 0, stream, a,
-                           tiles_n, scales);
+        hipLaunchKernelGGL((facewise_split_kernel<_Float16, CFG>), grid, block, 0, stream, a,
+                           tg, scales);
     } else {
         return hipErrorNotSupported;
     }

@@ -23,6 +23,7 @@
 
 #include "qt_internal.h"
 
+
 namespace qt {
 namespace detail {
 
@@ -162,12 +163,16 @@ __device__ __forceinline__ void unpack8(const unsigned (&w)[8], v8bf& hi, v8bf& 
     lo = __builtin_bit_cast(v8bf, l);
 }
 
-template <int MODE, int MT, int NT>
+template <int MODE, int MT, int NT, int NW = 4>
 __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int m0, int n0,
                                         float sa, float sb, V2Smem<MT, NT>& sm) {
     using H = typename std::conditional<MODE == 2, _Float16, __bf16>::type;
     using V8 = typename SplitTypes<H>::v8;
-    constexpr int MB = MT / 64, NB = NT / 64;
+    // NW waves as a (NW / 2) x 2 grid; each wave owns MB x NB 32 x 32 blocks
+    constexpr int WM = NW / 2;
+    constexpr int MB = MT / (32 * WM), NB = NT / 64;
+    static_assert(MB >= 1 && MT == 32 * WM * MB && (4 * (MT / 16)) % NW == 0 && (8 * (NT / 16)) % NW == 0,
+                  "tile shape does not fit the wave grid");
     constexpr int ABLK = MT / 16, BBLK = NT / 16;       // 1 KB blocks per plane
     constexpr int RB = 256 / NT, CQ = NT / 4;           // B block: RB k-rows of CQ 16-byte pieces
     const int tid = threadIdx.x, lane = tid & 63;
@@ -181,59 +186,68 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     const int nchunks = (a.n + KT - 1) / KT;
     const bool edge_tile = (m0 + MT > a.m) || (n0 + NT > a.s);
 
-    // ---- DMA of chunk c into buffer b (wave-uniform loops; 1 KB per instruction)
-    auto issue = [&](int c, int b) {
+    // ---- staging of chunk c: DTOT copy slots of 1 KB per wave (64 lanes x
+    // 16 B, lane L at byte 16 L of its LDS block); slot d < DA is an A block,
+    // the rest B blocks.  Interior chunks ("fast") use a wave-uniform base plus
+    // a per-lane offset fixed for the tile; other chunks clamp rows, columns
+    // and k to valid addresses (the compute masks those entries).
+    constexpr int DA = 4 * ABLK / NW, DB = 8 * BBLK / NW, DTOT = DA + DB;   // slots per wave per chunk
+    const int a_i = lane >> 2;
+    const int a_lane_off = a_i * a.lda + 4 * ((lane & 3) ^ ((a_i >> 2) & 3));
+    const int b_lane_off = (lane / CQ) * a.ldb + 4 * (lane % CQ);
+    // d is a compile-time constant at every call
+    auto slot_src = [&](int c, int d, bool fast) -> const float* {
         const int k0 = c * KT;
-#pragma unroll
-        for (int qq = 0; qq < ABLK; ++qq) {
-            const int q = 4 * qq + wave, pl = q / ABLK, blk = q % ABLK;
+        if (d < DA) {
+            const int q = NW * d + wave, pl = q / ABLK, blk = q % ABLK;
+            if (fast) return Af + pl * pa + (size_t)(m0 + blk * 16) * a.lda + k0 + a_lane_off;
             const int i = lane >> 2;
             const int kq = (lane & 3) ^ ((i >> 2) & 3);
             int grow = m0 + blk * 16 + i;
             grow = grow < a.m ? grow : a.m - 1;
             int gk = k0 + 4 * kq;
             gk = gk <= a.lda - 4 ? gk : a.lda - 4;
-            dma16(Af + pl * pa + (size_t)grow * a.lda + gk, &sm.A[b][pl][blk][0]);
+            return Af + pl * pa + (size_t)grow * a.lda + gk;
         }
-#pragma unroll
-        for (int qq = 0; qq < 2 * BBLK; ++qq) {
-            const int q = 4 * qq + wave, pl = q / BBLK, blk = q % BBLK;
-            // staged planes: 0..3 = B^[f] (B1r, B1i, B2r, B2i); 4..7 = D, E from
-            // B^[g]: Dr = -B2r, Di = B2i, Er = B1r, Ei = -B1i (signs applied later)
-            const int src = pl < 4 ? pl : (pl == 4 ? 2 : pl == 5 ? 3 : pl == 6 ? 0 : 1);
-            const float* base = (pl < 4 ? Bf : Bg) + src * pb;
-            int gk = k0 + blk * RB + lane / CQ;
-            gk = gk < a.n ? gk : a.n - 1;
-            int gc = n0 + 4 * (lane % CQ);
-            gc = gc <= a.ldb - 4 ? gc : a.ldb - 4;
-            dma16(base + (size_t)gk * a.ldb + gc, &sm.B[b][pl][blk][0]);
+        const int q = NW * (d - DA) + wave, pl = q / BBLK, blk = q % BBLK;
+        // staged planes: 0..3 = B^[f] (B1r, B1i, B2r, B2i); 4..7 = D, E from
+        // B^[g]: Dr = -B2r, Di = B2i, Er = B1r, Ei = -B1i (signs applied later)
+        const int src = pl < 4 ? pl : (pl == 4 ? 2 : pl == 5 ? 3 : pl == 6 ? 0 : 1);
+        const float* base = (pl < 4 ? Bf : Bg) + src * pb;
+        if (fast) return base + (size_t)(k0 + blk * RB) * a.ldb + n0 + b_lane_off;
+        int gk = k0 + blk * RB + lane / CQ;
+        gk = gk < a.n ? gk : a.n - 1;
+        int gc = n0 + 4 * (lane % CQ);
+        gc = gc <= a.ldb - 4 ? gc : a.ldb - 4;
+        return base + (size_t)gk * a.ldb + gc;
+    };
+    auto slot_dst = [&](int b, int d) -> float* {
+        if (d < DA) {
+            const int q = NW * d + wave;
+            return &sm.A[b][q / ABLK][q % ABLK][0];
         }
+        const int q = NW * (d - DA) + wave;
+        return &sm.B[b][q / BBLK][q % BBLK][0];
     };
 
-    // interior chunks: uniform (scalar) base per instruction + a per-lane
-    // offset that is the same for every chunk of the tile
-    const int a_i = lane >> 2;
-    const int a_lane_off = a_i * a.lda + 4 * ((lane & 3) ^ ((a_i >> 2) & 3));
-    const int b_lane_off = (lane / CQ) * a.ldb + 4 * (lane % CQ);
+    // DMA of chunk c into buffer b
+    auto issue = [&](int c, int b) {
+#pragma unroll
+        for (int d = 0; d < DTOT; ++d) dma16(slot_src(c, d, false), slot_dst(b, d));
+    };
+    auto issue_fast_one = [&](int c, int b, int d) { dma16(slot_src(c, d, true), slot_dst(b, d)); };
     auto issue_fast = [&](int c, int b) {
-        const int k0 = c * KT;
 #pragma unroll
-        for (int qq = 0; qq < ABLK; ++qq) {
-            const int q = 4 * qq + wave, pl = q / ABLK, blk = q % ABLK;
-            const float* ub = Af + pl * pa + (size_t)(m0 + blk * 16) * a.lda + k0;
-            dma16(ub + a_lane_off, &sm.A[b][pl][blk][0]);
-        }
+        for (int d = 0; d < DTOT; ++d) issue_fast_one(c, b, d);
+    };
+    // the share of plane step q (of 8) of the DMA of interior chunk c
+    auto issue_slice = [&](int c, int q) {
 #pragma unroll
-        for (int qq = 0; qq < 2 * BBLK; ++qq) {
-            const int q = 4 * qq + wave, pl = q / BBLK, blk = q % BBLK;
-            const int src = pl < 4 ? pl : (pl == 4 ? 2 : pl == 5 ? 3 : pl == 6 ? 0 : 1);
-            const float* ub = (pl < 4 ? Bf : Bg) + src * pb + (size_t)(k0 + blk * RB) * a.ldb + n0;
-            dma16(ub + b_lane_off, &sm.B[b][pl][blk][0]);
-        }
+        for (int d = q * DTOT / 8; d < (q + 1) * DTOT / 8; ++d) issue_fast_one(c, c & 1, d);
     };
     auto chunk_inside = [&](int c) { return !edge_tile && (c * KT + KT <= a.n); };
 
-    const int wm = wave & 1, wn = wave >> 1;
+    const int wm = wave % WM, wn = wave / WM;
     const int lr = lane & 31, lg = lane >> 5;
 
     v16f acc[4][MB][NB];
@@ -248,7 +262,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
 
     // ---- fragments of chunk c from buffer b; MASK zeroes out-of-range entries
     auto load_a = [&](int b, int mb, int c, bool mask, float (&x)[4][8]) {
-        const int rl = wm * (MT / 2) + mb * 32 + lr;
+        const int rl = wm * (MT / WM) + mb * 32 + lr;
         const int blk = rl >> 4, i = rl & 15;
         const int s0 = 4 * i + ((2 * lg) ^ ((i >> 2) & 3));
         const int s1 = 4 * i + ((2 * lg + 1) ^ ((i >> 2) & 3));
@@ -269,7 +283,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     // MODE 1 A fragments: raw split words, zeroed where masked
     auto load_a_words = [&](int b, int mb, int c, bool mask, unsigned (&w)[4][8]) {
         typedef unsigned u4 __attribute__((ext_vector_type(4)));
-        const int rl = wm * (MT / 2) + mb * 32 + lr;
+        const int rl = wm * (MT / WM) + mb * 32 + lr;
         const int blk = rl >> 4, i = rl & 15;
         const int s0 = 4 * i + ((2 * lg) ^ ((i >> 2) & 3));
         const int s1 = 4 * i + ((2 * lg + 1) ^ ((i >> 2) & 3));
@@ -300,7 +314,9 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     //   plane 7 Ei : ReC2 -= Ai2 Ei    ImC2 += Ar2 Ei
     // i.e. plane q feeds accumulators (q & 2 ? C2 : C1), real part from
     // A-plane (q & 1 ? Im : Re) and imaginary part from the other one.
-    auto compute = [&](int c, int b, bool mask) {
+    // inter: the DMA of interior chunk c + 1 is issued in slices between the
+    // plane steps (mask and inter are literals at every call)
+    auto compute = [&](int c, int b, bool mask, bool inter) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int cl = wn * (NT / 2) + nb * 32 + lr;
@@ -311,6 +327,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                 for (int mb = 0; mb < MB; ++mb) load_a(b, mb, c, mask, xa[mb]);
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
+                    if (inter) issue_slice(c + 1, q);
                     const float sgn = (q == 4 || q == 7) ? -1.f : 1.f;
                     float y[8], ny[8];
 #pragma unroll
@@ -353,18 +370,27 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                         for (int pl = 0; pl < 4; ++pl) split8<H>(xa[pl], ah[mb][pl], al[mb][pl]);
                     }
                 }
+                // all B words of the chunk are read up front, so that their LDS
+                // latency overlaps the products of the earlier planes
+                unsigned wb[8][8];
+                if constexpr (MODE == 1) {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    V8 yh, yl;
+                    for (int q = 0; q < 8; ++q)
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            const int k = 8 * lg + j;
+                            wb[q][j] = __builtin_bit_cast(unsigned, sm.B[b][q][k / RB][(k % RB) * NT + cl]);
+                        }
+                }
+                // B fragment (hi, lo) of staged plane q, D/E signs applied
+                auto bfrag = [&](int q, V8& yh, V8& yl) {
                     if constexpr (MODE == 1) {
                         const unsigned flip = (q == 4 || q == 7) ? 0x80008000u : 0u;
                         unsigned w[8];
 #pragma unroll
                         for (int j = 0; j < 8; ++j) {
-                            const int k = 8 * lg + j;
-                            const unsigned v = __builtin_bit_cast(unsigned, sm.B[b][q][k / RB][(k % RB) * NT + cl]);
-                            const bool ok = col_ok && (!mask || (c * KT + k < a.n));
-                            w[j] = ok ? (v ^ flip) : 0u;
+                            const bool ok = col_ok && (!mask || (c * KT + 8 * lg + j < a.n));
+                            w[j] = ok ? (wb[q][j] ^ flip) : 0u;
                         }
                         unpack8(w, yh, yl);
                     } else {
@@ -379,64 +405,86 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                         }
                         split8<H>(x, yh, yl);
                     }
-                    const int cre = (q & 2) ? 2 : 0;
-                    const int apl = (q & 4) ? 2 : 0;
-                    if ((q & 1) == 0) {
+                };
+                // Planes are taken in pairs (q, q + 2) = (0, 2), (1, 3), (4, 6),
+                // (5, 7): the first feeds C1, the second C2, so each of the three
+                // split products runs over 4 MB independent accumulator chains.
 #pragma unroll
-                        for (int mb = 0; mb < MB; ++mb) {
-                            v16f r = acc[cre][mb][nb], i = acc[cre + 1][mb][nb];
-                            r = mfma16<H>(al[mb][apl], yh, r);
-                            i = mfma16<H>(al[mb][apl + 1], yh, i);
-                            r = mfma16<H>(ah[mb][apl], yl, r);
-                            i = mfma16<H>(ah[mb][apl + 1], yl, i);
-                            r = mfma16<H>(ah[mb][apl], yh, r);
-                            i = mfma16<H>(ah[mb][apl + 1], yh, i);
-                            acc[cre][mb][nb] = r;
-                            acc[cre + 1][mb][nb] = i;
-                        }
-                    } else {
-                        const V8 nyh = neg8(yh), nyl = neg8(yl);
+                for (int qp = 0; qp < 4; ++qp) {
+                    const int qa = (qp & 1) | ((qp & 2) << 1), qb = qa + 2;
+                    if (inter) {
+                        issue_slice(c + 1, 2 * qp);
+                        issue_slice(c + 1, 2 * qp + 1);
+                    }
+                    V8 yh[2], yl[2], nyh[2], nyl[2];
+                    bfrag(qa, yh[0], yl[0]);
+                    bfrag(qb, yh[1], yl[1]);
+                    const bool odd = (qa & 1) != 0;          // imaginary B part: Re -= Ai Y, Im += Ar Y
+                    const int apl = (qa & 4) ? 2 : 0;        // A1 or A2
+                    if (odd) {
 #pragma unroll
-                        for (int mb = 0; mb < MB; ++mb) {
-                            v16f r = acc[cre][mb][nb], i = acc[cre + 1][mb][nb];
-                            r = mfma16<H>(al[mb][apl + 1], nyh, r);
-                            i = mfma16<H>(al[mb][apl], yh, i);
-                            r = mfma16<H>(ah[mb][apl + 1], nyl, r);
-                            i = mfma16<H>(ah[mb][apl], yl, i);
-                            r = mfma16<H>(ah[mb][apl + 1], nyh, r);
-                            i = mfma16<H>(ah[mb][apl], yh, i);
-                            acc[cre][mb][nb] = r;
-                            acc[cre + 1][mb][nb] = i;
+                        for (int t = 0; t < 2; ++t) {
+                            nyh[t] = neg8(yh[t]);
+                            nyl[t] = neg8(yl[t]);
                         }
                     }
+                    // lo x hi, hi x lo, then hi x hi (small terms first)
+#pragma unroll
+                    for (int step = 0; step < 3; ++step)
+#pragma unroll
+                        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                            for (int t = 0; t < 2; ++t) {
+                                const int cre = 2 * t;
+                                const V8 xr = step == 0 ? al[mb][apl] : ah[mb][apl];
+                                const V8 xi = step == 0 ? al[mb][apl + 1] : ah[mb][apl + 1];
+                                const V8 y = step == 1 ? yl[t] : yh[t];
+                                if (!odd) {
+                                    acc[cre][mb][nb] = mfma16<H>(xr, y, acc[cre][mb][nb]);
+                                    acc[cre + 1][mb][nb] = mfma16<H>(xi, y, acc[cre + 1][mb][nb]);
+                                } else {
+                                    const V8 ny = step == 1 ? nyl[t] : nyh[t];
+                                    acc[cre][mb][nb] = mfma16<H>(xi, ny, acc[cre][mb][nb]);
+                                    acc[cre + 1][mb][nb] = mfma16<H>(xr, y, acc[cre + 1][mb][nb]);
+                                }
+                            }
                 }
             }
         }
     };
 
-    auto advance = [&](int c) {
-        __builtin_amdgcn_s_waitcnt(0);       // this wave's DMA of chunk c has landed
-        __syncthreads();                     // ... and every wave's; chunk c - 1 is consumed
+    auto sync = [&]() {
+        __builtin_amdgcn_s_waitcnt(0);       // this wave's DMA of the chunk has landed
+        __syncthreads();                     // ... and every wave's; the previous chunk is consumed
+    };
+    if (chunk_inside(0)) issue_fast(0, 0);
+    else issue(0, 0);
+    // Unmasked chunks first, then the masked ones (a k tail, or every chunk of
+    // an edge tile): one compute variant per loop, so that the accumulators
+    // are defined in one place per loop and stay in AGPRs across iterations.
+    // While chunk c is multiplied, the DMA of chunk c + 1 goes out in slices
+    // between its plane steps.
+    const int nfull = edge_tile ? 0 : a.n / KT;
+    int c = 0;
+    for (; c + 1 < nfull; ++c) {             // chunk c + 1 is interior as well
+        sync();
+        compute(c, c & 1, false, true);
+    }
+    for (; c < nfull; ++c) {
+        sync();
         if (c + 1 < nchunks) {
             if (chunk_inside(c + 1)) issue_fast(c + 1, (c + 1) & 1);
             else issue(c + 1, (c + 1) & 1);
         }
-    };
-    if (chunk_inside(0)) issue_fast(0, 0);
-    else issue(0, 0);
-    // Two loops, each with a single compute variant, so that the accumulators
-    // are defined in one place per loop and stay in AGPRs across iterations.
-    const int nfull = edge_tile ? 0 : a.n / KT;
-    for (int c = 0; c < nfull; ++c) {
-        advance(c);
-        compute(c, c & 1, false);
+        compute(c, c & 1, false, false);
     }
-    for (int c = nfull; c < nchunks; ++c) {
-        advance(c);
-        compute(c, c & 1, true);
+    for (; c < nchunks; ++c) {
+        sync();
+        if (c + 1 < nchunks) issue(c + 1, (c + 1) & 1);
+        compute(c, c & 1, true, false);
     }
     __syncthreads();                         // LDS may be reused by the next tile
-    store_tile<MB, NB>(a, f, m0 + wm * (MT / 2), n0 + wn * (NT / 2), acc,
+    store_tile<MB, NB>(a, f, m0 + wm * (MT / WM), n0 + wn * (NT / 2), acc,
                        (MODE == 0) ? 1.f : 1.f / (sa * sb), lane);
 }
 
