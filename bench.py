@@ -50,6 +50,31 @@ def flops(m, n, s, p):
     return f_gemm, f_fft
 
 
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "facewise_split_bf16_c3_hbm_counters.md")
+KERNEL_SOURCES = ("facewise_impl.h", "facewise.hip", "qt_internal.h")
+
+
+def measured_traffic(workload, precision):
+    """Memory-side bytes per launch of the split product, from the committed
+    FETCH_SIZE / WRITE_SIZE summary (calibrated against a plain copy); None
+    when that summary does not cover this workload and precision or the
+    kernel sources have changed since the counters were taken."""
+    import hashlib
+    if workload != "c3" or precision != "split_bf16" or not os.path.exists(COUNTER_SUMMARY):
+        return None
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2212_14318_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    with open(COUNTER_SUMMARY) as fh:
+        for line in fh:
+            if line.startswith("traffic_bytes_per_launch:"):
+                tok = line.split()
+                if tok[3] == h.hexdigest():
+                    return float(tok[1])
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,9 +254,11 @@ def main():
     r = results[head]
     peak = PEAK_TFLOPS[head]
     roof = {"bound": "mfma", "achieved": round(r["gemm_tflops"], 3), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(r["gemm_tflops"] / peak, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(r["gemm_tflops"] / peak, 4),
+            "traffic": measured_traffic(args.workload, head),
             "kernel": "facewise coupled product (qt_fourier_tprod)",
-            "algorithmic_flops_per_launch": f_gemm}
+            "algorithmic_flops_per_launch": f_gemm,
+            "algorithmic_bytes_per_launch": 16.0 * p * (m * n + n * s + m * s)}
     if head.startswith("split"):
         roof["issued_frac"] = round(3 * r["gemm_tflops"] / peak, 4)
     dtype = {"fp32": "f32", "split_bf16": "bf16x3-split/f32-acc", "split_fp16": "fp16x3-split/f32-acc",
