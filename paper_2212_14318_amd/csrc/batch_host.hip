@@ -31,7 +31,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 // A problem's facewise phase then costs p ceil(m/MT) ceil(s/NT) t(cfg, n),
 // padding waste included, and the tuner picks the cheapest shape per problem.
 // The FFT radix order (detail::pick_radix policy 0 or 1) is picked per p by
-// timing the persistent FFT kernel with both.
+// timing the batched FFT kernel of that length with both.
 struct TuneTable {
     bool done = false;
     double alpha[NUM_TILE_CFGS] = {0, 0, 0};
@@ -217,7 +217,7 @@ int run_tuner(int prec, hipStream_t stream, TuneTable* out) {
             if (hipMemcpy(djob, &job, sizeof job, hipMemcpyHostToDevice) != hipSuccess) { fail = true; break; }
             hipError_t err = hipSuccess;
             const double sec = time_launch(
-                [&] { err = launch_batched_fft(false, djob, ditems, nitems, nitems, stream); }, stream);
+                [&] { err = launch_batched_fft(false, p, pol, djob, ditems, nitems, stream); }, stream);
             if (err != hipSuccess) { fail = true; break; }
             if (sec < best * 0.98) {   // switch only on a clear win
                 best = sec;
@@ -302,9 +302,15 @@ DescLayout desc_layout(int count, const qt_problem* probs) {
     return L;
 }
 
+// A run of FFT items with one tube length (and so one radix-order policy).
+struct FftBucket {
+    int p, pol, first, count;
+};
+
 struct HostLists {
     std::vector<BatchFftJob> fwd_jobs, inv_jobs;
     std::vector<BatchFftItem> fwd_items, inv_items;
+    std::vector<FftBucket> fwd_buckets, inv_buckets;
     std::vector<BatchGemmProb> probs;
     std::vector<BatchGemmItem> gitems;
 };
@@ -348,6 +354,16 @@ int build_lists(int count, const qt_problem* probs, int prec, char* ws, const De
     };
     std::stable_sort(H->fwd_items.begin(), H->fwd_items.end(), by_p(H->fwd_jobs));
     std::stable_sort(H->inv_items.begin(), H->inv_items.end(), by_p(H->inv_jobs));
+    auto buckets = [](const std::vector<BatchFftJob>& jobs, const std::vector<BatchFftItem>& items,
+                      std::vector<FftBucket>& out) {
+        for (int i = 0; i < (int)items.size(); ++i) {
+            const BatchFftJob& j = jobs[items[i].job];
+            if (out.empty() || out.back().p != j.p) out.push_back(FftBucket{j.p, j.pol, i, 0});
+            ++out.back().count;
+        }
+    };
+    buckets(H->fwd_jobs, H->fwd_items, H->fwd_buckets);
+    buckets(H->inv_jobs, H->inv_items, H->inv_buckets);
 
     std::vector<std::pair<double, BatchGemmItem>> g;
     for (int i = 0; i < count; ++i) {
@@ -388,28 +404,29 @@ int upload(const HostLists& H, char* ws, const DescLayout& L, hipStream_t stream
     return QT_OK;
 }
 
-struct Grids { int fft_fwd, gemm, fft_inv; };
-
-// Persistent grids: exactly the workgroups that can be resident at once.
-Grids grids(int prec) {
+// Persistent product grid: exactly the workgroups that can be resident at once.
+int gemm_grid(int prec) {
     int dev = current_device(), cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    return Grids{cus * batched_fft_fwd_blocks_per_cu(), cus * batched_gemm_blocks_per_cu(prec),
-                 cus * batched_fft_inv_blocks_per_cu()};
+    return cus * batched_gemm_blocks_per_cu(prec);
 }
 
 int enqueue(const HostLists& H, char* ws, const DescLayout& L, int prec, hipStream_t stream) {
-    const Grids gr = grids(prec);
     const auto* fj = reinterpret_cast<const BatchFftJob*>(ws + L.fwd_jobs);
     const auto* fi = reinterpret_cast<const BatchFftItem*>(ws + L.fwd_items);
     const auto* pj = reinterpret_cast<const BatchGemmProb*>(ws + L.probs);
     const auto* gi = reinterpret_cast<const BatchGemmItem*>(ws + L.gitems);
     const auto* ij = reinterpret_cast<const BatchFftJob*>(ws + L.inv_jobs);
     const auto* ii = reinterpret_cast<const BatchFftItem*>(ws + L.inv_items);
-    const int nf = (int)H.fwd_items.size(), ng = (int)H.gitems.size(), ni = (int)H.inv_items.size();
-    if (launch_batched_fft(false, fj, fi, nf, std::min(nf, gr.fft_fwd), stream) != hipSuccess) return QT_ERR_HIP;
-    if (launch_batched_gemm(prec, pj, gi, ng, std::min(ng, gr.gemm), stream) != hipSuccess) return QT_ERR_HIP;
-    if (launch_batched_fft(true, ij, ii, ni, std::min(ni, gr.fft_inv), stream) != hipSuccess) return QT_ERR_HIP;
+    const int ng = (int)H.gitems.size();
+    for (const FftBucket& b : H.fwd_buckets)
+        if (launch_batched_fft(false, b.p, b.pol, fj, fi + b.first, b.count, stream) != hipSuccess)
+            return QT_ERR_HIP;
+    if (launch_batched_gemm(prec, pj, gi, ng, std::min(ng, gemm_grid(prec)), stream) != hipSuccess)
+        return QT_ERR_HIP;
+    for (const FftBucket& b : H.inv_buckets)
+        if (launch_batched_fft(true, b.p, b.pol, ij, ii + b.first, b.count, stream) != hipSuccess)
+            return QT_ERR_HIP;
     return QT_OK;
 }
 

@@ -34,10 +34,10 @@ struct BatchGemmItem {
 // True if the persistent FFT kernel has a case for p (7-smooth, p <= 64).
 bool batched_fft_supported(int p);
 
-// Persistent tube FFT over a heterogeneous item list (grid blocks stride the
-// list).  Descriptor arrays are device pointers.
-hipError_t launch_batched_fft(bool inverse, const BatchFftJob* jobs, const BatchFftItem* items,
-                              int nitems, int grid, hipStream_t stream);
+// Tube FFT of nitems items that all have tube length p and radix-order
+// policy pol (one workgroup per item).  Descriptor arrays are device pointers.
+hipError_t launch_batched_fft(bool inverse, int p, int pol, const BatchFftJob* jobs,
+                              const BatchFftItem* items, int nitems, hipStream_t stream);
 
 // Persistent coupled facewise products over a heterogeneous tile list.
 // precision: 0 = FP32, 1 = split bf16.
@@ -47,9 +47,7 @@ hipError_t launch_batched_gemm(int precision, const BatchGemmProb* probs, const 
 // Dynamic LDS bytes of the persistent facewise kernel for a precision.
 size_t batched_gemm_smem_bytes(int precision);
 
-// Resident workgroups per CU of the persistent kernels (occupancy API).
+// Resident workgroups per CU of the persistent product kernel (occupancy API).
 int batched_gemm_blocks_per_cu(int precision);
-int batched_fft_fwd_blocks_per_cu();
-int batched_fft_inv_blocks_per_cu();
 
 }  // namespace qt

@@ -1,14 +1,14 @@
-// Batched T-products: persistent kernels, plan construction with hipGraph
-// capture, and the autotuner that picks tile shapes and FFT radix orders.
+// Batched T-products: the persistent product kernel and the dispatch of the
+// batched tube FFT.
 //
 // A batch of independent problems C_i = A_i * B_i (any m, n, s, p per
-// problem) runs as three persistent launches -- forward tube FFT of every A_i
-// and B_i, coupled facewise products of every (problem, frequency, tile), and
-// inverse tube FFT of every C_i^ -- each a fixed grid of workgroups striding a
-// heterogeneous work list sorted by estimated cost (longest first).  The
-// phases are ordered by the launch boundaries, so no workgroup ever waits on
-// another.  A plan captures the three launches into one hipGraph, so a
-// replay is a single hipGraphLaunch.
+// problem) runs in three phases: forward tube FFT of every A_i and B_i (one
+// launch per distinct tube length), coupled facewise products of every
+// (problem, frequency, tile) in one persistent launch whose fixed grid strides
+// a heterogeneous work list sorted by estimated cost (longest first), and the
+// inverse tube FFT of every C_i^.  The phases are ordered by the launch
+// boundaries, so no workgroup ever waits on another.  A plan captures all
+// launches into one hipGraph, so a replay is a single hipGraphLaunch.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -25,8 +25,8 @@
 
 namespace qt {
 
-hipError_t launch_batched_fft_fwd(const BatchFftJob*, const BatchFftItem*, int, int, hipStream_t);
-hipError_t launch_batched_fft_inv(const BatchFftJob*, const BatchFftItem*, int, int, hipStream_t);
+hipError_t launch_batched_fft_fwd(int, int, const BatchFftJob*, const BatchFftItem*, int, hipStream_t);
+hipError_t launch_batched_fft_inv(int, int, const BatchFftJob*, const BatchFftItem*, int, hipStream_t);
 
 namespace {
 
@@ -60,11 +60,11 @@ batched_gemm_kernel(const BatchGemmProb* __restrict__ probs, const BatchGemmItem
 
 }  // namespace
 
-hipError_t launch_batched_fft(bool inverse, const BatchFftJob* jobs, const BatchFftItem* items,
-                              int nitems, int grid, hipStream_t stream) {
+hipError_t launch_batched_fft(bool inverse, int p, int pol, const BatchFftJob* jobs,
+                              const BatchFftItem* items, int nitems, hipStream_t stream) {
     if (nitems <= 0) return hipSuccess;
-    return inverse ? launch_batched_fft_inv(jobs, items, nitems, grid, stream)
-                   : launch_batched_fft_fwd(jobs, items, nitems, grid, stream);
+    return inverse ? launch_batched_fft_inv(p, pol, jobs, items, nitems, stream)
+                   : launch_batched_fft_fwd(p, pol, jobs, items, nitems, stream);
 }
 
 size_t batched_gemm_smem_bytes(int precision) { return precision == 0 ? kF32Smem : kSplitSmem; }

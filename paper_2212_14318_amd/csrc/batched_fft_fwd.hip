@@ -1,4 +1,4 @@
-// Persistent forward tube FFT of the batched path.
+// Forward tube FFT of the batched path (one instance per tube length).
 #include "batched_fft_impl.h"
 
 namespace qt {
@@ -11,14 +11,8 @@ bool batched_fft_supported(int p) {
     }
 }
 
-hipError_t launch_batched_fft_fwd(const BatchFftJob* jobs, const BatchFftItem* items, int nitems,
-                                  int grid, hipStream_t stream) {
-    return detail::launch_batched_fft_impl<false>(jobs, items, nitems, grid, stream);
-}
-int batched_fft_fwd_blocks_per_cu() {
-    int n = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, detail::batched_fft_kernel<false>, 256, 0);
-    return (e == hipSuccess && n > 0) ? n : 1;
+hipError_t launch_batched_fft_fwd(int p, int pol, const BatchFftJob* jobs, const BatchFftItem* items,
+                                  int nitems, hipStream_t stream) {
+    return detail::launch_batched_fft_impl<false>(p, pol, jobs, items, nitems, stream);
 }
 }  // namespace qt

@@ -244,6 +244,9 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     auto issue_slice = [&](int c, int q) {
 #pragma unroll
         for (int d = q * DTOT / 8; d < (q + 1) * DTOT / 8; ++d) issue_fast_one(c, c & 1, d);
+        // keep the slice here: the scheduler would otherwise sink the DMA to
+        // the end of the chunk, where its latency is no longer hidden
+        __builtin_amdgcn_sched_barrier(0);
     };
     auto chunk_inside = [&](int c) { return !edge_tile && (c * KT + KT <= a.n); };
 
