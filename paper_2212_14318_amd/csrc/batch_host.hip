@@ -312,7 +312,8 @@ struct HostLists {
     std::vector<BatchFftItem> fwd_items, inv_items;
     std::vector<FftBucket> fwd_buckets, inv_buckets;
     std::vector<BatchGemmProb> probs;
-    std::vector<BatchGemmItem> gitems;
+    std::vector<BatchGemmItem> gitems;      // grouped by tile shape, longest first in each group
+    int gfirst[detail::NUM_TILE_CFGS] = {0, 0, 0}, gcount[detail::NUM_TILE_CFGS] = {0, 0, 0};
 };
 
 void add_fft_items(std::vector<BatchFftItem>& items, int job, long positions) {
@@ -339,9 +340,7 @@ int build_lists(int count, const qt_problem* probs, int prec, char* ws, const De
         H->fwd_jobs.push_back(BatchFftJob{(const float*)q.A, Ah, tw.f32, q.m, q.n, q.n, lda, q.p, pol, pack, 0});
         H->fwd_jobs.push_back(BatchFftJob{(const float*)q.B, Bh, tw.f32, q.n, q.s, q.s, ldb, q.p, pol, pack, 0});
         H->inv_jobs.push_back(BatchFftJob{Ch, (float*)q.C, tw.f32, q.m, q.s, ldc, q.s, q.p, pol, 0, 0});
-        // the persistent kernel carries the 128x64 and 64x64 shapes
-        const int cfg = pick_tile(&tune, q.m, q.n, q.s,
-                                  (1u << detail::TILE_128x64) | (1u << detail::TILE_64x64));
+        const int cfg = pick_tile(&tune, q.m, q.n, q.s);
         H->probs.push_back(BatchGemmProb{FacewiseArgs<float>{Ah, Bh, Ch, q.m, q.n, q.s, q.p, lda, ldb, ldc},
                                          cfg, 0, 0, 0});
     }
@@ -377,7 +376,13 @@ int build_lists(int count, const qt_problem* probs, int prec, char* ws, const De
     }
     std::stable_sort(g.begin(), g.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
     H->gitems.reserve(g.size());
-    for (auto& e : g) H->gitems.push_back(e.second);
+    // one persistent launch per tile shape: group the (sorted) items by shape
+    for (int cfg = 0; cfg < detail::NUM_TILE_CFGS; ++cfg) {
+        H->gfirst[cfg] = (int)H->gitems.size();
+        for (auto& e : g)
+            if (H->probs[e.second.prob].cfg == cfg) H->gitems.push_back(e.second);
+        H->gcount[cfg] = (int)H->gitems.size() - H->gfirst[cfg];
+    }
     if ((long)H->fwd_items.size() > L.n_fwd_items_max || (long)H->gitems.size() > L.n_gitems_max ||
         (long)H->inv_items.size() > L.n_inv_items_max)
         return QT_ERR_INVALID_ARG;   // cannot happen: the layout is an upper bound
@@ -404,11 +409,12 @@ int upload(const HostLists& H, char* ws, const DescLayout& L, hipStream_t stream
     return QT_OK;
 }
 
-// Persistent product grid: exactly the workgroups that can be resident at once.
-int gemm_grid(int prec) {
+// Persistent product grid of a tile shape: exactly the workgroups that can be
+// resident at once.
+int gemm_grid(int prec, int cfg) {
     int dev = current_device(), cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    return cus * batched_gemm_blocks_per_cu(prec);
+    return cus * batched_gemm_blocks_per_cu(prec, cfg);
 }
 
 int enqueue(const HostLists& H, char* ws, const DescLayout& L, int prec, hipStream_t stream) {
@@ -418,12 +424,15 @@ int enqueue(const HostLists& H, char* ws, const DescLayout& L, int prec, hipStre
     const auto* gi = reinterpret_cast<const BatchGemmItem*>(ws + L.gitems);
     const auto* ij = reinterpret_cast<const BatchFftJob*>(ws + L.inv_jobs);
     const auto* ii = reinterpret_cast<const BatchFftItem*>(ws + L.inv_items);
-    const int ng = (int)H.gitems.size();
     for (const FftBucket& b : H.fwd_buckets)
         if (launch_batched_fft(false, b.p, b.pol, fj, fi + b.first, b.count, stream) != hipSuccess)
             return QT_ERR_HIP;
-    if (launch_batched_gemm(prec, pj, gi, ng, std::min(ng, gemm_grid(prec)), stream) != hipSuccess)
-        return QT_ERR_HIP;
+    for (int cfg = 0; cfg < detail::NUM_TILE_CFGS; ++cfg) {
+        const int n = H.gcount[cfg];
+        if (n && launch_batched_gemm(prec, cfg, pj, gi + H.gfirst[cfg], n, std::min(n, gemm_grid(prec, cfg)),
+                                     stream) != hipSuccess)
+            return QT_ERR_HIP;
+    }
     for (const FftBucket& b : H.inv_buckets)
         if (launch_batched_fft(true, b.p, b.pol, ij, ii + b.first, b.count, stream) != hipSuccess)
             return QT_ERR_HIP;
@@ -543,8 +552,6 @@ int qt_batched_plan_create(int count, const qt_problem* probs, int precision, vo
     st = qt::upload(H, (char*)ws, L, stream);
     if (st != QT_OK) return st;
     if (hipStreamSynchronize(stream) != hipSuccess) return QT_ERR_HIP;
-    // make the kernel attributes current before capturing (a zero-item call)
-    if (qt::launch_batched_gemm(precision, nullptr, nullptr, 0, 1, stream) != hipSuccess) return QT_ERR_HIP;
 
     hipStream_t cap = nullptr;
     if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return QT_ERR_HIP;

@@ -39,15 +39,12 @@ bool batched_fft_supported(int p);
 hipError_t launch_batched_fft(bool inverse, int p, int pol, const BatchFftJob* jobs,
                               const BatchFftItem* items, int nitems, hipStream_t stream);
 
-// Persistent coupled facewise products over a heterogeneous tile list.
-// precision: 0 = FP32, 1 = split bf16.
-hipError_t launch_batched_gemm(int precision, const BatchGemmProb* probs, const BatchGemmItem* items,
-                               int nitems, int grid, hipStream_t stream);
+// Persistent coupled facewise products over a list of tiles that all have
+// tile shape cfg (detail::TileCfg).  precision: 0 = FP32, 1 = split bf16.
+hipError_t launch_batched_gemm(int precision, int cfg, const BatchGemmProb* probs,
+                               const BatchGemmItem* items, int nitems, int grid, hipStream_t stream);
 
-// Dynamic LDS bytes of the persistent facewise kernel for a precision.
-size_t batched_gemm_smem_bytes(int precision);
-
-// Resident workgroups per CU of the persistent product kernel (occupancy API).
-int batched_gemm_blocks_per_cu(int precision);
+// Resident workgroups per CU of the persistent product kernel of a shape.
+int batched_gemm_blocks_per_cu(int precision, int cfg);
 
 }  // namespace qt

@@ -26,10 +26,6 @@ namespace {
 
 using namespace detail;
 
-// Waves per workgroup of a tile shape: the 128 x 64 tile runs 8 waves (4 x 2,
-// each 32 x 32), so two waves share a SIMD and hide each other's LDS and
-// VALU latency; the 64-wide tiles run 4 waves (2 x 2).
-__host__ __device__ constexpr int tile_waves(int cfg) { return cfg == TILE_128x64 ? 8 : 4; }
 
 // Workgroup -> (frequency, tile row, tile column) over a 1-D grid.
 struct TileGrid {

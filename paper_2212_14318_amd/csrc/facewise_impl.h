@@ -14,10 +14,11 @@
 //   Re C2 = Ar1 Br2f - Ai1 Bi2f + Ar2 Br1g + Ai2 Bi1g
 //   Im C2 = Ar1 Bi2f + Ai1 Br2f + Ai2 Br1g - Ar2 Bi1g
 // i.e. 16 real products = 32 m n s flops per frequency (the count of the
-// proof of Theorem 5.2, additions included).  A workgroup (4 waves, 2 x 2)
-// owns an MT x NT tile of all four output planes and stages the four A planes
-// and the eight B planes (f and g) of one 16-deep k-chunk in LDS, so each B
-// value is read once per output tile rather than once per output plane.
+// proof of Theorem 5.2, additions included).  A workgroup (NW waves in an
+// (NW / 2) x 2 grid) owns an MT x NT tile of all four output planes and stages
+// the four A planes and the eight B planes (f and g) of one 16-deep k-chunk in
+// LDS, so each B value is read once per output tile rather than once per
+// output plane.
 #pragma once
 #include <type_traits>
 
@@ -61,8 +62,11 @@ __device__ __forceinline__ void store_tile(const FacewiseArgs<float>& a, int f, 
 // x = hi + lo with hi = rn(x), lo = rn(x - hi) in a 16-bit format; a real
 // product X Y is taken as Xhi Yhi + Xhi Ylo + Xlo Yhi (the dropped Xlo Ylo is
 // ~2^-16 relative for bf16), each on v_mfma_f32_32x32x16_{bf16,f16} with FP32
-// accumulation.  The Fourier-domain tensors stay FP32 in HBM (same bytes as
-// the FP32 path); the split happens when MFMA fragments are formed.
+// accumulation.  The split operands take the same bytes in HBM as FP32 ones:
+// for bf16 the forward tube FFT writes every real as one word hi | lo << 16
+// and the fragments are unpacked with byte permutes; for fp16 the operands
+// stay FP32 (the scale depends on the whole frequency) and are scaled and
+// split when the fragments are formed.
 //
 // The coupled products are rewritten as two plain complex products,
 //   C1^ = A1^ B1^[f] + A2^ D,  D = -conj(B2^[g]),
@@ -103,15 +107,21 @@ __device__ __forceinline__ V8 neg8(V8 x) {
 enum TileCfg { TILE_128x64 = 0, TILE_64x128 = 1, TILE_64x64 = 2, NUM_TILE_CFGS = 3 };
 __host__ __device__ constexpr int tile_mt(int cfg) { return cfg == TILE_128x64 ? 128 : 64; }
 __host__ __device__ constexpr int tile_nt(int cfg) { return cfg == TILE_64x128 ? 128 : 64; }
+// Waves per workgroup of a tile shape: the 128 x 64 tile runs 8 waves (4 x 2,
+// each 32 x 32), so two waves share a SIMD and hide each other's LDS and
+// VALU latency; the 64-wide tiles run 4 waves (2 x 2).
+__host__ __device__ constexpr int tile_waves(int cfg) { return cfg == TILE_128x64 ? 8 : 4; }
 
 
-// ===================================================================== v2
-// Pipelined tile routine shared by the FP32 and split paths:
+// ======================================================== pipelined tile
+// Tile routine shared by the FP32 and split paths:
 //  * k-chunks of 16 go global -> LDS by DMA (global_load_lds_dwordx4: each
 //    wave instruction moves 64 x 16 B into 1 KB of LDS, lane L at byte 16 L),
 //    so no prefetch registers are live across the MFMA loop;
-//  * two LDS buffers, one barrier per chunk: the DMA of chunk c + 1 runs
-//    while chunk c is multiplied;
+//  * two LDS buffers, one barrier per chunk: the DMA of chunk c + 1 goes out
+//    in slices between the plane steps of chunk c;
+//  * B planes are consumed in pairs (q, q + 2) feeding C1 and C2, which gives
+//    4 MB independent accumulator chains per split product;
 //  * within a chunk, lane group g = lane / 32 owns logical k = 8 g .. 8 g + 7
 //    of both operands (any assignment works as long as A and B agree), so an
 //    A fragment is 8 contiguous floats (two 16-byte LDS reads) and a B
