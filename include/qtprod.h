@@ -157,11 +157,13 @@ typedef struct {
 /* Workspace bytes for qt_tprod_batched over `count` problems (host array). */
 size_t qt_batched_workspace_size(int count, const qt_problem* probs, int precision);
 
-/* C_i = A_i * B_i for count independent problems of any sizes and p: three
- * persistent launches (forward tube FFT of every A_i, B_i; coupled facewise
- * products of every frequency and output tile; inverse tube FFT of every
- * C_i^), each walking a cost-sorted work list, after a small descriptor upload
- * into ws (from pageable memory, so the call returns once it is staged).
+/* C_i = A_i * B_i for count independent problems of any sizes and p, in three
+ * phases: the forward tube FFT of every A_i, B_i (one launch per distinct p,
+ * one workgroup per 256 tubes); the coupled facewise products of every
+ * frequency and output tile (one persistent launch per tile shape, walking a
+ * cost-sorted work list); the inverse tube FFT of every C_i^ (one launch per
+ * distinct p).  A small descriptor upload into ws comes first, from pageable
+ * memory, so the call returns once it is staged.
  * probs is a HOST array read before the call returns.  Each problem obeys the
  * single-call preconditions; outputs must not overlap any input or output.
  * precision: QT_FP32 or QT_SPLIT_BF16; every p must be 7-smooth and <= 64.
@@ -171,8 +173,8 @@ size_t qt_batched_workspace_size(int count, const qt_problem* probs, int precisi
 int qt_tprod_batched(int count, const qt_problem* probs, int precision,
                      void* ws, size_t ws_bytes, hipStream_t stream);
 
-/* Batched plan: the work lists of one batch, built once, with the three
- * persistent launches captured into a hipGraph.  The plan refers to the
+/* Batched plan: the work lists of one batch, built once, with all launches of
+ * the three phases captured into one hipGraph.  The plan refers to the
  * problems' buffers and to `ws`, which must stay allocated (and untouched by
  * other work while a replay runs) until qt_batched_plan_destroy. */
 typedef struct qt_batched_plan_s* qt_batched_plan;
@@ -197,7 +199,7 @@ int qt_batched_plan_destroy(qt_batched_plan plan);
  * QT_TUNE_CACHE) the autotuner for `precision` on the current device: it times
  * every facewise tile shape on a calibration problem to fit the per-tile cost
  * model t = alpha + beta * ceil(n / 16), and times both radix orders of the
- * persistent FFT for every batched p.  Allocates scratch memory and
+ * batched tube FFT for every batched p.  Allocates scratch memory and
  * synchronises `stream`.  Single-problem calls then use the cost model for
  * their tile shape too. */
 int qt_autotune(int precision, hipStream_t stream);
