@@ -33,7 +33,8 @@ batched_gemm_kernel(const BatchGemmProb* __restrict__ probs, const BatchGemmItem
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const BatchGemmItem item = items[it];
         const BatchGemmProb pr = probs[item.prob];
-        tile_v2<PREC, MT, NT, tile_waves(CFG)>(pr.a, item.f, item.tm * MT, item.tn * NT, 1.f, 1.f, sm);
+        tile_v2<PREC, MT, NT, tile_waves(CFG), plane_groups(PREC, CFG)>(pr.a, item.f, item.tm * MT,
+                                                                         item.tn * NT, 1.f, 1.f, sm);
     }
 }
 

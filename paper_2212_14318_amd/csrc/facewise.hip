@@ -64,7 +64,7 @@ facewise_split_kernel(FacewiseArgs<float> a, TileGrid tg, const float* __restric
         sa = scales[f];
         sb = scales[a.p + f];
     }
-    tile_v2<MODE, MT, NT, tile_waves(CFG)>(a, f, tm * MT, tn * NT, sa, sb, sm);
+    tile_v2<MODE, MT, NT, tile_waves(CFG), plane_groups(MODE, CFG)>(a, f, tm * MT, tn * NT, sa, sb, sm);
 }
 
 // ---------------------------------------------------------------- FP64 VALU

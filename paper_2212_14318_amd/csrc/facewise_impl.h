@@ -34,7 +34,7 @@ constexpr int KT = 16;     // k-chunk depth
 
 // 32x32 f32 accumulator layout of v_mfma_f32_32x32x*: register r of lane l
 // holds row 8 (r / 4) + 4 (l / 32) + (r % 4), column l % 32.
-template <int MB, int NB>
+template <int MB, int NB, int C0 = 0, int NC = 4>
 __device__ __forceinline__ void store_tile(const FacewiseArgs<float>& a, int f, int row0, int col0,
                                            const v16f (&acc)[4][MB][NB], float scale, int lane) {
     const size_t pc = (size_t)a.p * a.m * a.ldc;
@@ -51,7 +51,7 @@ __device__ __forceinline__ void store_tile(const FacewiseArgs<float>& a, int f, 
                 const int row = row0 + mb * 32 + 8 * (r >> 2) + 4 * lk + (r & 3);
                 if (row < a.m) {
 #pragma unroll
-                    for (int c = 0; c < 4; ++c)
+                    for (int c = C0; c < C0 + NC; ++c)
                         Cf[c * pc + (size_t)row * a.ldc + col] = acc[c][mb][nb][r] * scale;
                 }
             }
@@ -111,6 +111,10 @@ __host__ __device__ constexpr int tile_nt(int cfg) { return cfg == TILE_64x128 ?
 // each 32 x 32), so two waves share a SIMD and hide each other's LDS and
 // VALU latency; the 64-wide tiles run 4 waves (2 x 2).
 __host__ __device__ constexpr int tile_waves(int cfg) { return cfg == TILE_128x64 ? 8 : 4; }
+// The split-bf16 128 x 64 tile splits its 8 waves into two plane groups
+// (tile_v2's PG): each wave reads half the staged planes per chunk, which cuts
+// LDS fragment reads and unpacking by a third.
+__host__ __device__ constexpr bool plane_groups(int mode, int cfg) { return mode == 1 && cfg == TILE_128x64; }
 
 
 // ======================================================== pipelined tile
@@ -161,7 +165,8 @@ __device__ __forceinline__ void split8(const float (&x)[8], typename SplitTypes<
 
 // Split-bf16 operand words (hi | lo << 16, written by the tube FFT) -> the
 // hi and lo fragments of 8 consecutive k (one v_perm_b32 per pair).
-__device__ __forceinline__ void unpack8(const unsigned (&w)[8], v8bf& hi, v8bf& lo) {
+template <typename V8>
+__device__ __forceinline__ void unpack8(const unsigned (&w)[8], V8& hi, V8& lo) {
     typedef unsigned u4 __attribute__((ext_vector_type(4)));
     u4 h, l;
 #pragma unroll
@@ -169,17 +174,22 @@ __device__ __forceinline__ void unpack8(const unsigned (&w)[8], v8bf& hi, v8bf& 
         h[j] = __builtin_amdgcn_perm(w[2 * j + 1], w[2 * j], 0x05040100u);
         l[j] = __builtin_amdgcn_perm(w[2 * j + 1], w[2 * j], 0x07060302u);
     }
-    hi = __builtin_bit_cast(v8bf, h);
-    lo = __builtin_bit_cast(v8bf, l);
+    hi = __builtin_bit_cast(V8, h);
+    lo = __builtin_bit_cast(V8, l);
 }
 
-template <int MODE, int MT, int NT, int NW = 4>
+template <int MODE, int MT, int NT, int NW = 4, bool PG = false>
 __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int m0, int n0,
                                         float sa, float sb, V2Smem<MT, NT>& sm) {
     using H = typename std::conditional<MODE == 2, _Float16, __bf16>::type;
     using V8 = typename SplitTypes<H>::v8;
-    // NW waves as a (NW / 2) x 2 grid; each wave owns MB x NB 32 x 32 blocks
-    constexpr int WM = NW / 2;
+    // NW waves as a (NW / 2) x 2 grid; each wave owns MB x NB 32 x 32 blocks.
+    // PG (split bf16): two plane groups of NW / 2 waves, each a (NW / 4) x 2
+    // grid over the whole tile; group 0 takes the B^[f] planes with A1, group
+    // 1 the D, E planes with A2, and the partial sums meet once per tile.
+    static_assert(!PG || MODE == 1, "plane groups are built for the split-bf16 path");
+    constexpr int WG = PG ? NW / 2 : NW;
+    constexpr int WM = WG / 2;
     constexpr int MB = MT / (32 * WM), NB = NT / 64;
     static_assert(MB >= 1 && MT == 32 * WM * MB && (4 * (MT / 16)) % NW == 0 && (8 * (NT / 16)) % NW == 0,
                   "tile shape does not fit the wave grid");
@@ -260,7 +270,9 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     };
     auto chunk_inside = [&](int c) { return !edge_tile && (c * KT + KT <= a.n); };
 
-    const int wm = wave % WM, wn = wave / WM;
+    const int grp = PG ? wave / WG : 0;                  // plane group (wave-uniform)
+    const int tw = PG ? wave % WG : wave;
+    const int wm = tw % WM, wn = tw / WM;
     const int lr = lane & 31, lg = lane >> 5;
 
     v16f acc[4][MB][NB];
@@ -466,39 +478,181 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
         }
     };
 
+    // PG: chunk c for plane group G, i.e. staged B planes 4 G .. 4 G + 3 and
+    // A planes 2 G, 2 G + 1; pairs (q, q + 2) feed C1 and C2 as in compute.
+    auto compute_pg = [&](auto G, int c, int b, bool mask, bool inter) {
+        constexpr int g0 = decltype(G)::value;
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int cl = wn * (NT / 2) + nb * 32 + lr;
+            const bool col_ok = !mask || (n0 + cl < a.s);
+            V8 ah[MB][2], al[MB][2];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const int rl = wm * (MT / WM) + mb * 32 + lr;
+                const int blk = rl >> 4, i = rl & 15;
+                const int s0 = 4 * i + ((2 * lg) ^ ((i >> 2) & 3));
+                const int s1 = 4 * i + ((2 * lg + 1) ^ ((i >> 2) & 3));
+                const bool row_ok = !mask || (m0 + rl < a.m);
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int pl = 2 * g0 + t;
+                    const u4 u = *reinterpret_cast<const u4*>(&sm.A[b][pl][blk][4 * s0]);
+                    const u4 v = *reinterpret_cast<const u4*>(&sm.A[b][pl][blk][4 * s1]);
+                    const unsigned x[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+                    unsigned w[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const bool ok = row_ok && (!mask || (c * KT + 8 * lg + j < a.n));
+                        w[j] = ok ? x[j] : 0u;
+                    }
+                    unpack8(w, ah[mb][t], al[mb][t]);
+                }
+            }
+            unsigned wb[4][8];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int k = 8 * lg + j;
+                    wb[q][j] = __builtin_bit_cast(unsigned, sm.B[b][4 * g0 + q][k / RB][(k % RB) * NT + cl]);
+                }
+            auto bfrag = [&](int q, V8& yh, V8& yl) {
+                const unsigned flip = (q == 4 || q == 7) ? 0x80008000u : 0u;
+                unsigned w[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const bool ok = col_ok && (!mask || (c * KT + 8 * lg + j < a.n));
+                    w[j] = ok ? (wb[q - 4 * g0][j] ^ flip) : 0u;
+                }
+                unpack8(w, yh, yl);
+            };
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int qa = 4 * g0 + k, qb = qa + 2;
+                if (inter) {
+#pragma unroll
+                    for (int i4 = 0; i4 < 4; ++i4) issue_slice(c + 1, 4 * k + i4);
+                }
+                V8 yh[2], yl[2], nyh[2], nyl[2];
+                bfrag(qa, yh[0], yl[0]);
+                bfrag(qb, yh[1], yl[1]);
+                const bool odd = k == 1;                 // imaginary B part: Re -= Ai Y, Im += Ar Y
+                if (odd) {
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        nyh[t] = neg8(yh[t]);
+                        nyl[t] = neg8(yl[t]);
+                    }
+                }
+#pragma unroll
+                for (int step = 0; step < 3; ++step)
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                        for (int t = 0; t < 2; ++t) {
+                            const int cre = 2 * t;
+                            const V8 xr = step == 0 ? al[mb][0] : ah[mb][0];
+                            const V8 xi = step == 0 ? al[mb][1] : ah[mb][1];
+                            const V8 y = step == 1 ? yl[t] : yh[t];
+                            if (!odd) {
+                                acc[cre][mb][nb] = mfma16<H>(xr, y, acc[cre][mb][nb]);
+                                acc[cre + 1][mb][nb] = mfma16<H>(xi, y, acc[cre + 1][mb][nb]);
+                            } else {
+                                const V8 ny = step == 1 ? nyl[t] : nyh[t];
+                                acc[cre][mb][nb] = mfma16<H>(xi, ny, acc[cre][mb][nb]);
+                                acc[cre + 1][mb][nb] = mfma16<H>(xr, y, acc[cre + 1][mb][nb]);
+                            }
+                        }
+            }
+        }
+    };
+
     auto sync = [&]() {
         __builtin_amdgcn_s_waitcnt(0);       // this wave's DMA of the chunk has landed
         __syncthreads();                     // ... and every wave's; the previous chunk is consumed
     };
     if (chunk_inside(0)) issue_fast(0, 0);
     else issue(0, 0);
-    // Unmasked chunks first, then the masked ones (a k tail, or every chunk of
-    // an edge tile): one compute variant per loop, so that the accumulators
-    // are defined in one place per loop and stay in AGPRs across iterations.
-    // While chunk c is multiplied, the DMA of chunk c + 1 goes out in slices
-    // between its plane steps.
     const int nfull = edge_tile ? 0 : a.n / KT;
-    int c = 0;
-    for (; c + 1 < nfull; ++c) {             // chunk c + 1 is interior as well
-        sync();
-        compute(c, c & 1, false, true);
-    }
-    for (; c < nfull; ++c) {
-        sync();
-        if (c + 1 < nchunks) {
-            if (chunk_inside(c + 1)) issue_fast(c + 1, (c + 1) & 1);
-            else issue(c + 1, (c + 1) & 1);
+    const float scale = (MODE == 0) ? 1.f : 1.f / (sa * sb);
+    // The k loop and the epilogue, for plane group G (a compile-time constant,
+    // so register arrays are indexed statically; both groups run the same
+    // sequence of barriers).
+    auto run = [&](auto G) {
+        auto comp = [&](int c, int b, bool mask, bool inter) {
+            if constexpr (PG) compute_pg(G, c, b, mask, inter);
+            else compute(c, b, mask, inter);
+        };
+        // Unmasked chunks first, then the masked ones (a k tail, or every
+        // chunk of an edge tile): one compute variant per loop, so that the
+        // accumulators are defined in one place per loop and stay in AGPRs
+        // across iterations.  While chunk c is multiplied, the DMA of chunk
+        // c + 1 goes out in slices between its plane steps.
+        int c = 0;
+        for (; c + 1 < nfull; ++c) {         // chunk c + 1 is interior as well
+            sync();
+            comp(c, c & 1, false, true);
         }
-        compute(c, c & 1, false, false);
+        for (; c < nfull; ++c) {
+            sync();
+            if (c + 1 < nchunks) {
+                if (chunk_inside(c + 1)) issue_fast(c + 1, (c + 1) & 1);
+                else issue(c + 1, (c + 1) & 1);
+            }
+            comp(c, c & 1, false, false);
+        }
+        for (; c < nchunks; ++c) {
+            sync();
+            if (c + 1 < nchunks) issue(c + 1, (c + 1) & 1);
+            comp(c, c & 1, true, false);
+        }
+        __syncthreads();                     // the staging buffers are free
+        const int row0 = m0 + wm * (MT / WM), col0 = n0 + wn * (NT / 2);
+        if constexpr (PG) {
+            // group 0 stores C1 (planes 0, 1), group 1 stores C2 (planes 2, 3);
+            // each hands the other its partial sums of the other's planes
+            constexpr int g0 = decltype(G)::value;
+            constexpr int send = g0 == 0 ? 2 : 0, keep = g0 == 0 ? 0 : 2;
+            constexpr int NREG = 2 * MB * NB * 16, LANES = 64 * WG;
+            static_assert(2 * NREG * LANES * sizeof(float) <= sizeof(V2Smem<MT, NT>),
+                          "reduction does not fit the staging buffers");
+            float* red = reinterpret_cast<float*>(&sm);
+            float* mine = red + (size_t)g0 * NREG * LANES;
+            const float* theirs = red + (size_t)(1 - g0) * NREG * LANES;
+            const int slot = tw * 64 + lane;
+            int idx = 0;
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) mine[(size_t)(idx++) * LANES + slot] = acc[send + c2][mb][nb][r];
+            __syncthreads();
+            idx = 0;
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) acc[keep + c2][mb][nb][r] += theirs[(size_t)(idx++) * LANES + slot];
+            __syncthreads();                 // LDS may be reused by the next tile
+            store_tile<MB, NB, keep, 2>(a, f, row0, col0, acc, scale, lane);
+        } else {
+            store_tile<MB, NB>(a, f, row0, col0, acc, scale, lane);
+        }
+    };
+    if constexpr (PG) {
+        if (grp == 0) run(std::integral_constant<int, 0>{});
+        else run(std::integral_constant<int, 1>{});
+    } else {
+        run(std::integral_constant<int, 0>{});
     }
-    for (; c < nchunks; ++c) {
-        sync();
-        if (c + 1 < nchunks) issue(c + 1, (c + 1) & 1);
-        compute(c, c & 1, true, false);
-    }
-    __syncthreads();                         // LDS may be reused by the next tile
-    store_tile<MB, NB>(a, f, m0 + wm * (MT / WM), n0 + wn * (NT / 2), acc,
-                       (MODE == 0) ? 1.f : 1.f / (sa * sb), lane);
 }
 
 }  // namespace detail
