@@ -59,20 +59,31 @@ def measured_traffic(workload, precision):
     FETCH_SIZE / WRITE_SIZE summary (calibrated against a plain copy); None
     when that summary does not cover this workload and precision or the
     kernel sources have changed since the counters were taken."""
-    import hashlib
     if workload != "c3" or precision != "split_bf16" or not os.path.exists(COUNTER_SUMMARY):
         return None
-    h = hashlib.sha1()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2212_14318_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    fp = kernel_fingerprint()
     with open(COUNTER_SUMMARY) as fh:
         for line in fh:
             if line.startswith("traffic_bytes_per_launch:"):
                 tok = line.split()
-                if tok[3] == h.hexdigest():
+                if tok[3] == fp:
                     return float(tok[1])
     return None
+
+
+def kernel_fingerprint():
+    """SHA-1 of the product kernel's sources with comments and whitespace
+    removed, so that only code changes invalidate a counter measurement."""
+    import hashlib
+    import re
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2212_14318_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
+    return h.hexdigest()
 
 
 def parse():

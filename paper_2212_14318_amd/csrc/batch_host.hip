@@ -487,8 +487,8 @@ int validate(int count, const qt_problem* probs, int prec, void* ws, size_t ws_b
 
 int choose_tile(int m, int n, int s, int precision) {
     TuneTable t;
-    if (!tuned(precision, &t)) return detail::TILE_128x64;
-    return pick_tile(&t, m, n, s);
+    // untuned: the shape with the least padded area (ties: 128 x 64)
+    return pick_tile(tuned(precision, &t) ? &t : nullptr, m, n, s);
 }
 
 }  // namespace qt

@@ -115,7 +115,8 @@ hipError_t launch_conj_transpose(const ConjTJob<T>* jobs, int njobs, hipStream_t
 int get_twiddles(int p, hipStream_t stream, Twiddles* out);
 
 // Tile shape (detail::TileCfg) for one facewise product: from the autotuner's
-// cost model when it has run on this device for this precision, else 128x64.
+// cost model when it has run on this device for this precision, else the
+// shape with the least padded area (ties go to 128x64).
 int choose_tile(int m, int n, int s, int precision);
 
 }  // namespace qt
