@@ -134,7 +134,8 @@ def tprod_backward(A: torch.Tensor, B: torch.Tensor, G: torch.Tensor, precision=
 
 
 def tprod_batched(As, Bs, precision="fp32", outs=None):
-    """[A_i * B_i] for lists of tensors, in one persistent launch."""
+    """[A_i * B_i] for lists of tensors in one call of the batched path
+    (tube FFTs per distinct p, one persistent product launch per tile shape)."""
     prec = _prec(precision)
     if len(As) != len(Bs) or not As:
         raise ValueError("need equally many A and B tensors (at least one)")
