@@ -9,7 +9,7 @@ import torch
 import oracle
 import synth
 from paper_2212_14318_amd import _native as nat
-from paper_2212_14318_amd import tprod, tube_fft
+from paper_2212_14318_amd import fourier_tprod, tprod, tube_fft
 
 from gpu_util import device, rel_err, sample_indices, sampled_rel_err, to_dev, to_np
 
@@ -64,6 +64,28 @@ def test_tube_fft_split_words(p):
     assert rel_err(hi + lo, want) < 2e-5
     assert rel_err(hi, want) < 1e-2          # hi alone is only a bf16 rounding
     assert np.all(np.abs(lo) <= np.abs(hi) * 2.0 ** -8 + 1e-30)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("m,n,s,p", [(300, 50, 150, 12), (250, 33, 65, 8), (130, 17, 70, 5),
+                                     (129, 16, 65, 3), (64, 1, 64, 2)])
+def test_staged_path_ragged(m, n, s, p, prec):
+    """The three stages called one by one (qt_tube_fft, qt_fourier_tprod,
+    inverse qt_tube_fft), with padded Fourier row strides.  qt_fourier_tprod
+    always runs the 128 x 64 tile (for split-bf16 the two-plane-group
+    kernel), so these shapes pin its edge tiles, k tails and padding."""
+    A = synth.quat_tensor(m, n, p, seed=700 + m)
+    B = synth.quat_tensor(n, s, p, seed=800 + s)
+    lda, ldb = nat.qt_fourier_ld(n), nat.qt_fourier_ld(s)
+    dev = device()
+    Ah = torch.full((4, p, m, lda), float("nan"), device=dev)
+    Bh = torch.full((4, p, n, ldb), float("nan"), device=dev)
+    tube_fft(to_dev(A), precision=prec, out=Ah)
+    tube_fft(to_dev(B), precision=prec, out=Bh)
+    Ch = fourier_tprod(Ah, Bh, n, s, precision=prec)
+    C = torch.empty((4, p, m, s), device=dev)
+    tube_fft(Ch, inverse=True, cols=s, out=C)
+    assert rel_err(to_np(C), oracle.tprod(A, B)) < TOLS[prec]
 
 
 @pytest.mark.parametrize("p", [1, 3, 8, 16, 30, 64])
