@@ -37,6 +37,8 @@ WORKLOADS = {
                            "(seeds 5000/5001)"),
     "c4": dict(cfg=4, desc="512 independent T-products, m,n,s ~ U{16..256}, p ~ U{8,12,16,30,32,45,64}, "
                            "N(0,1) (sizes seed 4000, problem i seed 4100000+i)"),
+    "chain": dict(cfg=3, desc="chain (A * B) * C, A, B, C 1024x1024x32 quaternion, N(0,1) "
+                              "(seeds 3000/3001/3002), kept in the Fourier domain between the products"),
 }
 
 
@@ -132,6 +134,8 @@ def main():
         return bench_batched(args, wl, dev, stream)
     if args.workload == "c5" and args.backward:
         return bench_backward(args, wl, dev, stream)
+    if args.workload == "chain":
+        return bench_chain(args, wl, dev, stream)
     t0 = time.time()
     inputs = synth.config_inputs(cfg)
     A64, B64 = inputs[0], inputs[1]
@@ -387,6 +391,66 @@ def bench_backward(args, wl, dev, stream):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "bf16x3-split/f32-acc" if head == "split_bf16" else "f32", "data": "synthetic",
            "config": {"workload": wl["desc"] + " + backward", "precision": head, "flops_per_step": F},
+           "per_precision": res, "roofline": None, "cpu_baseline": None})
+
+
+def bench_chain(args, wl, dev, stream):
+    """Fourier-domain-resident chain D = (A * B) * C: three forward transforms,
+    two coupled products (split-bf16: the FP32 intermediate is turned into
+    operand words in place) and one inverse transform, against two qt_tprod
+    calls.  value = F(A * B) + F((A * B) * C) over the resident chain's time."""
+    import torch
+
+    import synth
+    from paper_2212_14318_amd import _native as nat
+    from paper_2212_14318_amd import fourier_tprod, split_words, tprod, tube_fft
+
+    A64, B64 = synth.config_inputs(3)[:2]
+    _, p, m, n = A64.shape
+    C64 = synth.quat_tensor(n, n, p, seed=3002)
+    A, B, C = (torch.from_numpy(x).to(dev, torch.float32) for x in (A64, B64, C64))
+    ld = nat.qt_fourier_ld(n)
+    Ah, Bh, Ch = (torch.empty((4, p, n, ld), device=dev) for _ in range(3))
+    D = torch.empty((4, p, n, n), device=dev)
+    fg, ff = flops(n, n, n, p)
+    F = 2 * (fg + ff)
+    res = {}
+    precs = [x for x in args.precisions.split(",") if x]
+    for prec in precs:
+        def resident():
+            tube_fft(A, precision=prec, out=Ah)
+            tube_fft(B, precision=prec, out=Bh)
+            tube_fft(C, precision=prec, out=Ch)
+            Xh = fourier_tprod(Ah, Bh, n, n, precision=prec)
+            if prec == "split_bf16":
+                split_words(Xh, cols=n)
+            Dh = fourier_tprod(Xh, Ch, n, n, precision=prec, out=Ah)
+            tube_fft(Dh, inverse=True, cols=n, out=D)
+
+        def two_calls():
+            tprod(tprod(A, B, prec), C, prec, out=D)
+
+        times = {}
+        for name, fn in (("resident", resident), ("two_calls", two_calls)):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn()
+            torch.cuda.synchronize()
+            times[name] = (time.perf_counter() - t0) * 1e3 / args.steps
+        res[prec] = {"ms_per_step": times["resident"], "two_calls_ms": times["two_calls"],
+                     "tflops_equiv": F / (times["resident"] * 1e-3) / 1e12}
+        log(f"[bench] chain {prec}: resident {times['resident']:.3f} ms, two qt_tprod calls "
+            f"{times['two_calls']:.3f} ms, {res[prec]['tflops_equiv']:.1f} TFLOP/s-equiv")
+    head = precs[0]
+    _emit({"metric": "T-product TFLOP/s-equiv & % roofline, split-BF16 vs FP32 at stated rel. error",
+           "value": round(res[head]["tflops_equiv"], 3), "unit": "TFLOP/s-equiv", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res[head]["ms_per_step"], 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16x3-split/f32-acc" if head == "split_bf16" else "f32", "data": "synthetic",
+           "config": {"workload": wl["desc"], "precision": head, "flops_per_step": F},
            "per_precision": res, "roofline": None, "cpu_baseline": None})
 
 

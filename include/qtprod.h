@@ -133,6 +133,17 @@ int qt_tube_fft(int rows, int cols, int p, const void* X, int ldx, void* Xh, int
 int qt_fourier_tprod(int m, int n, int s, int p, const void* Ah, int lda, const void* Bh,
                      int ldb, void* Ch, int ldc, int precision, hipStream_t stream);
 
+/* In place: turn a Fourier-domain FP32 tensor Xh [4][p][rows][ld] (e.g. the
+ * C^ written by qt_fourier_tprod) into the QT_SPLIT_BF16 operand format, the
+ * word hi | lo << 16 per real (hi = rn_bf16(x), lo = rn_bf16(x - hi)), which
+ * is what qt_tube_fft writes for QT_SPLIT_BF16.  This keeps chains
+ * A * B * C ... in the Fourier domain for the split-bf16 products: since
+ * bcirc(A * B) = bcirc(A) bcirc(B) (proof of Theorem 5.1), the product of two
+ * transformed tensors is the transform of A * B, ready to be multiplied
+ * again.  Columns beyond cols are untouched.  ld >= cols, a multiple of 4;
+ * Xh 16-byte aligned.  Returns QT_OK, QT_ERR_INVALID_ARG or QT_ERR_HIP. */
+int qt_split_words(int rows, int cols, int p, void* Xh, int ld, hipStream_t stream);
+
 /* Workspace bytes needed by qt_tprod for these sizes and precision
  * (0 if an argument is invalid).  Holds the Fourier-domain tensors
  * A^, B^ and C^ (row strides rounded up to a multiple of 4 reals). */

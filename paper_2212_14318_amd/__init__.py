@@ -12,8 +12,8 @@ Cayley-Dickson parts X1 = a + b i and X2 = c + d i.
     C = tprod(A, B, precision="fp32")     # or "split_bf16", "fp64"
     C = qtprod(A, B)                      # differentiable (autograd.Function)
 """
-from .ops import (BatchedPlan, QTProd, autotune, fourier_tprod, qtprod, tprod,  # noqa: F401
+from .ops import (BatchedPlan, QTProd, autotune, fourier_tprod, qtprod, split_words, tprod,  # noqa: F401
                   tprod_backward, tprod_batched, tube_fft)
 from ._native import PRECISIONS, QtError  # noqa: F401
 
-__all__ = ["tprod", "tube_fft", "fourier_tprod", "BatchedPlan", "autotune", "tprod_backward", "tprod_batched", "qtprod", "QTProd", "PRECISIONS", "QtError"]
+__all__ = ["tprod", "tube_fft", "fourier_tprod", "split_words", "BatchedPlan", "autotune", "tprod_backward", "tprod_batched", "qtprod", "QTProd", "PRECISIONS", "QtError"]

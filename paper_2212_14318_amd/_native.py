@@ -43,6 +43,7 @@ SIGNATURES = {
     "qt_fourier_ld": (_I, [_I]),
     "qt_tube_fft": (_I, [_I, _I, _I, _P, _I, _P, _I, _I, _I, _P]),
     "qt_fourier_tprod": (_I, [_I, _I, _I, _I, _P, _I, _P, _I, _P, _I, _I, _P]),
+    "qt_split_words": (_I, [_I, _I, _I, _P, _I, _P]),
     "qt_workspace_size": (_SZ, [_I, _I, _I, _I, _I]),
     "qt_tprod": (_I, [_I, _I, _I, _I, _P, _P, _P, _I, _P, _SZ, _P]),
     "qt_batched_workspace_size": (_SZ, [_I, ctypes.POINTER(qt_problem), _I]),
@@ -111,6 +112,10 @@ def qt_tube_fft(rows, cols, p, X, ldx, Xh, ldh, inverse, precision, stream=0) ->
 
 def qt_fourier_tprod(m, n, s, p, Ah, lda, Bh, ldb, Ch, ldc, precision, stream=0) -> int:
     return lib().qt_fourier_tprod(m, n, s, p, Ah, lda, Bh, ldb, Ch, ldc, precision, stream)
+
+
+def qt_split_words(rows, cols, p, Xh, ld, stream=0) -> int:
+    return lib().qt_split_words(rows, cols, p, Xh, ld, stream)
 
 
 def qt_workspace_size(m: int, n: int, s: int, p: int, precision: int) -> int:

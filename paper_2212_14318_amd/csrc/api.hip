@@ -335,6 +335,12 @@ int qt_fourier_tprod(int m, int n, int s, int p, const void* Ah, int lda, const 
     return e == hipSuccess ? QT_OK : QT_ERR_HIP;
 }
 
+int qt_split_words(int rows, int cols, int p, void* Xh, int ld, hipStream_t stream) {
+    if (!dims_ok(rows, cols, p) || !Xh || !aligned16(Xh)) return QT_ERR_INVALID_ARG;
+    if (ld < cols || (ld & 3) || !dims_ok(rows, ld, p)) return QT_ERR_INVALID_ARG;
+    return hip_status(qt::launch_split_words((float*)Xh, 4L * p, rows, cols, ld, stream));
+}
+
 size_t qt_workspace_size(int m, int n, int s, int p, int precision) {
     if (!valid_precision(precision) || !dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p))
         return 0;

@@ -114,6 +114,10 @@ hipError_t launch_conj_transpose(const ConjTJob<T>* jobs, int njobs, hipStream_t
 // first use on `stream`, which is then synchronised once).  Returns a qt_status.
 int get_twiddles(int p, hipStream_t stream, Twiddles* out);
 
+// In-place FP32 -> split-bf16 words of `faces` faces of rows x cols (row
+// stride ld, a multiple of 4).
+hipError_t launch_split_words(float* X, long faces, long rows, long cols, long ld, hipStream_t stream);
+
 // Tile shape (detail::TileCfg) for one facewise product: from the autotuner's
 // cost model when it has run on this device for this precision, else the
 // shape with the least padded area (ties go to 128x64).

@@ -1,0 +1,51 @@
+// Conversion of a Fourier-domain FP32 tensor into the split-bf16 operand
+// format, in place: every real x becomes the word hi | lo << 16 with
+// hi = rn_bf16(x), lo = rn_bf16(x - hi) -- the words the forward tube FFT
+// writes for QT_SPLIT_BF16.  It lets the FP32 output of one coupled product
+// (qt_fourier_tprod) feed the next split-bf16 product without leaving the
+// Fourier domain: bcirc(A * B) = bcirc(A) bcirc(B) (proof of Theorem 5.1), so
+// products of block-diagonalised tensors chain frequency by frequency.
+#include "fft_impl.h"
+
+namespace qt {
+namespace {
+
+// grid-stride over (face, row, 4-column group); ld is a multiple of 4, so a
+// group is one aligned 16-byte access
+__global__ void __launch_bounds__(256)
+split_words_kernel(float* __restrict__ X, long faces, long rows, long cols, long ld) {
+    const long groups = (cols + 3) / 4;
+    const long total = faces * rows * groups;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const long g = e % groups;
+        const long fr = e / groups;                      // face * rows + row
+        float* row = X + fr * ld + 4 * g;
+        const int n = (int)(cols - 4 * g < 4 ? cols - 4 * g : 4);
+        if (n == 4) {
+            float4 v = *reinterpret_cast<const float4*>(row);
+            uint4 w;
+            w.x = detail::split_bf16_word(v.x);
+            w.y = detail::split_bf16_word(v.y);
+            w.z = detail::split_bf16_word(v.z);
+            w.w = detail::split_bf16_word(v.w);
+            *reinterpret_cast<uint4*>(row) = w;
+        } else {
+            for (int j = 0; j < n; ++j)
+                reinterpret_cast<unsigned*>(row)[j] = detail::split_bf16_word(row[j]);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_split_words(float* X, long faces, long rows, long cols, long ld, hipStream_t stream) {
+    const long total = faces * rows * ((cols + 3) / 4);
+    if (total <= 0) return hipSuccess;
+    long blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(split_words_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, X, faces, rows, cols,
+                       ld);
+    return hipGetLastError();
+}
+
+}  // namespace qt

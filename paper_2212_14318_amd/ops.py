@@ -88,6 +88,17 @@ def fourier_tprod(Ah: torch.Tensor, Bh: torch.Tensor, n: int, s: int, precision=
     return out
 
 
+def split_words(Xh: torch.Tensor, cols=None) -> torch.Tensor:
+    """In place: Fourier-domain FP32 tensor (4, p, rows, ld) -> split-bf16
+    operand words (the first `cols` columns, default ld); returns Xh."""
+    _check_tensor(Xh, "Xh", nat.QT_FP32)
+    _, p, rows, ld = Xh.shape
+    cols = ld if cols is None else cols
+    st = nat.qt_split_words(rows, cols, p, Xh.data_ptr(), ld, _stream(Xh.device))
+    nat.check(st, "qt_split_words")
+    return Xh
+
+
 def tprod(A: torch.Tensor, B: torch.Tensor, precision="fp32", out: torch.Tensor | None = None,
           ws: torch.Tensor | None = None) -> torch.Tensor:
     """C = A * B (T-product of quaternion tensors) on the GPU."""

@@ -121,6 +121,15 @@ def test_fourier_tprod_rejects_bad_args():
     assert nat.qt_fourier_ld(5) == 8 and nat.qt_fourier_ld(8) == 8 and nat.qt_fourier_ld(0) == 0
 
 
+def test_split_words_rejects_bad_args():
+    buf = ctypes.c_void_p(4096)          # never dereferenced: rejected before any launch
+    assert nat.qt_split_words(0, 4, 4, buf, 4, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_split_words(4, 4, 4, None, 4, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_split_words(4, 5, 4, buf, 5, None) == nat.QT_ERR_INVALID_ARG   # ld not a multiple of 4
+    assert nat.qt_split_words(4, 8, 4, buf, 4, None) == nat.QT_ERR_INVALID_ARG   # ld < cols
+    assert nat.qt_split_words(4, 4, 4, ctypes.c_void_p(4098), 4, None) == nat.QT_ERR_INVALID_ARG
+
+
 def test_prepare_rejects_bad_p():
     assert nat.qt_prepare(0, None) == nat.QT_ERR_INVALID_ARG
     assert nat.qt_prepare(nat.QT_MAX_P + 1, None) == nat.QT_ERR_UNSUPPORTED
