@@ -37,6 +37,8 @@ WORKLOADS = {
                            "(seeds 5000/5001)"),
     "c4": dict(cfg=4, desc="512 independent T-products, m,n,s ~ U{16..256}, p ~ U{8,12,16,30,32,45,64}, "
                            "N(0,1) (sizes seed 4000, problem i seed 4100000+i)"),
+    "matvec": dict(cfg=6, desc="block-circulant quaternion mat-vec: A 2048x2048x16, B 2048x1x16 quaternion, "
+                                "N(0,1) (seeds 6000/6001), coupled product on resident Fourier operands"),
     "chain": dict(cfg=3, desc="chain (A * B) * C, A, B, C 1024x1024x32 quaternion, N(0,1) "
                               "(seeds 3000/3001/3002), kept in the Fourier domain between the products"),
 }
@@ -136,6 +138,8 @@ def main():
         return bench_backward(args, wl, dev, stream)
     if args.workload == "chain":
         return bench_chain(args, wl, dev, stream)
+    if args.workload == "matvec":
+        return bench_matvec(args, wl, dev, stream)
     t0 = time.time()
     inputs = synth.config_inputs(cfg)
     A64, B64 = inputs[0], inputs[1]
@@ -452,6 +456,68 @@ def bench_chain(args, wl, dev, stream):
            "dtype": "bf16x3-split/f32-acc" if head == "split_bf16" else "f32", "data": "synthetic",
            "config": {"workload": wl["desc"], "precision": head, "flops_per_step": F},
            "per_precision": res, "roofline": None, "cpu_baseline": None})
+
+
+def bench_matvec(args, wl, dev, stream):
+    """Narrow coupled product (s = 1): A^ is read once from HBM, so the
+    roofline is HBM bandwidth over 16 m n p bytes (plus the small B^, C^).
+    The 64-column MFMA tile path at s = 5 is timed beside it."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from paper_2212_14318_amd import _native as nat
+    from paper_2212_14318_amd import fourier_tprod, tube_fft
+
+    m = n = 2048
+    p = 16
+    A64 = synth.quat_tensor(m, n, p, seed=6000)
+    A = torch.from_numpy(A64).to(dev, torch.float32)
+    res = {}
+    precs = [x for x in args.precisions.split(",") if x]
+    for s_cols in (1, 5):
+        B64 = synth.quat_tensor(n, s_cols, p, seed=6001)
+        B = torch.from_numpy(B64).to(dev, torch.float32)
+        for prec in precs:
+            Ah = tube_fft(A, precision=prec, out=torch.empty((4, p, m, nat.qt_fourier_ld(n)), device=dev))
+            Bh = tube_fft(B, precision=prec, out=torch.empty((4, p, n, nat.qt_fourier_ld(s_cols)), device=dev))
+            Ch = torch.empty((4, p, m, nat.qt_fourier_ld(s_cols)), device=dev)
+            for _ in range(args.warmup):
+                fourier_tprod(Ah, Bh, n, s_cols, precision=prec, out=Ch)
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record(stream)
+            for _ in range(args.steps):
+                fourier_tprod(Ah, Bh, n, s_cols, precision=prec, out=Ch)
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[1]) / args.steps
+            nbytes = 16.0 * p * (m * n + 2 * n * s_cols + m * s_cols)
+            res[f"{prec}_s{s_cols}"] = {"ms": ms, "gbps": nbytes / (ms * 1e-3) / 1e9,
+                                        "tflops_equiv": 32.0 * m * n * s_cols * p / (ms * 1e-3) / 1e12}
+            if s_cols == 1:
+                C = torch.empty((4, p, m, 1), device=dev)
+                tube_fft(Ch, inverse=True, cols=1, out=C)
+                kk = np.arange(p)
+                ii = np.random.Generator(np.random.PCG64(7)).integers(0, m, p)
+                ref = oracle.tprod_entries(A64, B64, kk, ii, np.zeros(p, dtype=np.int64))
+                got = C.cpu().numpy()[:, kk, ii, 0].astype(np.float64)
+                res[f"{prec}_s1"]["rel_err"] = float(np.sqrt(((got - ref) ** 2).sum() / (ref ** 2).sum()))
+            log(f"[bench] matvec {prec} s={s_cols}: {ms:.3f} ms, {res[f'{prec}_s{s_cols}']['gbps']:.0f} GB/s "
+                f"of A^ + B^ + C^" + (f", rel err {res[f'{prec}_s1']['rel_err']:.2e}" if s_cols == 1 else ""))
+            del Ah, Bh, Ch
+    head = precs[0]
+    r = res[f"{head}_s1"]
+    _emit({"metric": "T-product TFLOP/s-equiv & % roofline, split-BF16 vs FP32 at stated rel. error",
+           "value": round(r["tflops_equiv"], 4), "unit": "TFLOP/s-equiv", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms"], 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": wl["desc"], "precision": head},
+           "roofline": {"bound": "hbm", "achieved": round(r["gbps"], 1), "peak": PEAK_HBM_GBPS,
+                        "unit": "GB/s", "frac": round(r["gbps"] / PEAK_HBM_GBPS, 4), "traffic": None},
+           "per_precision": res, "cpu_baseline": None})
 
 
 if __name__ == "__main__":

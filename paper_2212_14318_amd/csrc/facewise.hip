@@ -119,6 +119,107 @@ __global__ void __launch_bounds__(256) facewise_f64_valu(FacewiseArgs<double> a)
     }
 }
 
+// ---------------------------------------------------- narrow products (s <= 4)
+// A block-circulant quaternion matrix times a few tube vectors (s <= 4; the
+// circulant mat-vec of Theorems 4.2 / 4.3 when m = n = s = 1): the coupled
+// product is then bound by reading A^ once from HBM, which a 64-column MFMA
+// tile would do with ~1/64 of its work useful.  FP32 VALU: a block owns 16
+// output rows of one frequency (4 waves x 4 rows), stages B^[f] and B^[-f]
+// for k-tiles of 256 in LDS, and reads A^ coalesced along k; lanes own k,
+// and the 64 partial sums of every output meet in a wave reduction.  Split-
+// bf16 operand words are decoded to hi + lo (exact in FP32).
+constexpr int kNarrowRows = 16, kNarrowK = 256;
+
+template <bool WORDS>
+__device__ __forceinline__ float operand(float x) {
+    if constexpr (WORDS) {
+        const unsigned w = __builtin_bit_cast(unsigned, x);
+        return __builtin_bit_cast(float, w << 16) + __builtin_bit_cast(float, w & 0xFFFF0000u);
+    } else {
+        return x;
+    }
+}
+
+template <int S, bool WORDS>
+__global__ void __launch_bounds__(256) facewise_narrow_kernel(FacewiseArgs<float> a) {
+    __shared__ float sb[8][S][kNarrowK];          // planes 0..3 = B^[f], 4..7 = B^[-f]
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int f = blockIdx.y, g = (a.p - f) % a.p;
+    const int row0 = blockIdx.x * kNarrowRows + wave * 4;
+    const size_t pa = (size_t)a.p * a.m * a.lda, pb = (size_t)a.p * a.n * a.ldb;
+    const size_t pc = (size_t)a.p * a.m * a.ldc;
+    const float* Af = a.Ah + (size_t)f * a.m * a.lda;
+    const float* Bf = a.Bh + (size_t)f * a.n * a.ldb;
+    const float* Bg = a.Bh + (size_t)g * a.n * a.ldb;
+    float c[4][4][S];                              // [row][plane][column]
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < S; ++j) c[r][q][j] = 0.f;
+    for (int k0 = 0; k0 < a.n; k0 += kNarrowK) {
+        __syncthreads();                           // previous tile consumed
+        for (int e = threadIdx.x; e < 8 * S * kNarrowK; e += 256) {
+            const int kk = e % kNarrowK, j = (e / kNarrowK) % S, q = e / (kNarrowK * S);
+            const int k = k0 + kk;
+            float v = 0.f;
+            if (k < a.n) v = operand<WORDS>((q < 4 ? Bf : Bg)[(q & 3) * pb + (size_t)k * a.ldb + j]);
+            sb[q][j][kk] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kNarrowK / 64; ++u) {
+            const int kk = u * 64 + lane, k = k0 + kk;
+            if (k >= a.n) break;                   // k >= n only in the last tile
+            float b[8][S];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int j = 0; j < S; ++j) b[q][j] = sb[q][j][kk];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = row0 + r;
+                if (i >= a.m) break;
+                const float* Ai = Af + (size_t)i * a.lda + k;
+                const float ar1 = operand<WORDS>(Ai[0]), ai1 = operand<WORDS>(Ai[pa]);
+                const float ar2 = operand<WORDS>(Ai[2 * pa]), ai2 = operand<WORDS>(Ai[3 * pa]);
+#pragma unroll
+                for (int j = 0; j < S; ++j) {
+                    // C1 = A1 B1^[f] - A2 conj(B2^[g]),  C2 = A1 B2^[f] + A2 conj(B1^[g])
+                    c[r][0][j] += ar1 * b[0][j] - ai1 * b[1][j] - ar2 * b[6][j] - ai2 * b[7][j];
+                    c[r][1][j] += ar1 * b[1][j] + ai1 * b[0][j] + ar2 * b[7][j] - ai2 * b[6][j];
+                    c[r][2][j] += ar1 * b[2][j] - ai1 * b[3][j] + ar2 * b[4][j] + ai2 * b[5][j];
+                    c[r][3][j] += ar1 * b[3][j] + ai1 * b[2][j] + ai2 * b[4][j] - ar2 * b[5][j];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                float v = c[r][q][j];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                c[r][q][j] = v;
+            }
+    if (lane == 0) {
+        float* Cf = a.Ch + (size_t)f * a.m * a.ldc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = row0 + r;
+            if (i >= a.m) break;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int j = 0; j < S; ++j) Cf[q * pc + (size_t)i * a.ldc + j] = c[r][q][j];
+        }
+    }
+}
+
 // ------------------------------------------------ fp16 power-of-two scales
 // fp16 has a 5-bit exponent, so the split operands are scaled by a power of
 // two before the split: per frequency f, sa[f] for the four planes of A^[f],
@@ -214,8 +315,27 @@ static hipError_t launch_cfg(const FacewiseArgs<float>& a, int precision, const 
     return hipGetLastError();
 }
 
+template <int S>
+static hipError_t launch_narrow(const FacewiseArgs<float>& a, bool words, hipStream_t stream) {
+    const dim3 grid((unsigned)((a.m + kNarrowRows - 1) / kNarrowRows), (unsigned)a.p), block(256);
+    if (words) hipLaunchKernelGGL((facewise_narrow_kernel<S, true>), grid, block, 0, stream, a);
+    else hipLaunchKernelGGL((facewise_narrow_kernel<S, false>), grid, block, 0, stream, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_facewise_f32(const FacewiseArgs<float>& a, int precision, hipStream_t stream,
                                int tile_cfg, const float* scales) {
+    if (precision < 0 || precision > 2) return hipErrorNotSupported;
+    if (a.s <= kNarrowMaxS) {
+        // HBM-bound shape: FP32 VALU on the (decoded) operands, any precision
+        const bool words = precision == 1;
+        switch (a.s) {
+            case 1: return launch_narrow<1>(a, words, stream);
+            case 2: return launch_narrow<2>(a, words, stream);
+            case 3: return launch_narrow<3>(a, words, stream);
+            default: return launch_narrow<4>(a, words, stream);
+        }
+    }
     switch (tile_cfg) {
         case TILE_128x64: return launch_cfg<TILE_128x64>(a, precision, scales, stream);
         case TILE_64x128: return launch_cfg<TILE_64x128>(a, precision, scales, stream);

@@ -81,6 +81,10 @@ struct FacewiseArgs {
     int lda, ldb, ldc;
 };
 
+// Products with at most this many columns (s) run the narrow FP32 VALU kernel
+// in every float precision (they are bound by reading A^, not by MFMA).
+constexpr int kNarrowMaxS = 4;
+
 // C^[f] = A^[f] B^[f] coupled with -f (see qtprod.h) for every f.
 // precision: 0 = FP32 MFMA, 1 = split bf16, 2 = split fp16 (float only; needs
 // `scales`: 2p power-of-two scales, [f] for A^ and [p + f] for B^).
