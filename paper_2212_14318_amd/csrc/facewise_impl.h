@@ -123,7 +123,8 @@ __host__ __device__ constexpr bool plane_groups(int mode, int cfg) { return mode
 //    wave instruction moves 64 x 16 B into 1 KB of LDS, lane L at byte 16 L),
 //    so no prefetch registers are live across the MFMA loop;
 //  * two LDS buffers, one barrier per chunk: the DMA of chunk c + 1 goes out
-//    in slices between the plane steps of chunk c;
+//    in slices between the plane steps of chunk c (with plane groups, whole,
+//    from group 1 before its fragment reads);
 //  * B planes are consumed in pairs (q, q + 2) feeding C1 and C2, which gives
 //    4 MB independent accumulator chains per split product;
 //  * within a chunk, lane group g = lane / 32 owns logical k = 8 g .. 8 g + 7
@@ -197,6 +198,8 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     constexpr int RB = 256 / NT, CQ = NT / 4;           // B block: RB k-rows of CQ 16-byte pieces
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform (SGPR)
+    const int grp = PG ? wave / WG : 0;                  // plane group (wave-uniform)
+    const int tw = PG ? wave % WG : wave;
     const int g = (a.p - f) % a.p;
     const size_t pa = (size_t)a.p * a.m * a.lda;
     const size_t pb = (size_t)a.p * a.n * a.ldb;
@@ -215,11 +218,12 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     const int a_i = lane >> 2;
     const int a_lane_off = a_i * a.lda + 4 * ((lane & 3) ^ ((a_i >> 2) & 3));
     const int b_lane_off = (lane / CQ) * a.ldb + 4 * (lane % CQ);
-    // d is a compile-time constant at every call
-    auto slot_src = [&](int c, int d, bool fast) -> const float* {
+    // Block q (0 <= q < 4 * ABLK) of the A chunk or block q (0 <= q < 8 *
+    // BBLK) of the B chunk.
+    auto block_src = [&](int c, bool isA, int q, bool fast) -> const float* {
         const int k0 = c * KT;
-        if (d < DA) {
-            const int q = NW * d + wave, pl = q / ABLK, blk = q % ABLK;
+        if (isA) {
+            const int pl = q / ABLK, blk = q % ABLK;
             if (fast) return Af + pl * pa + (size_t)(m0 + blk * 16) * a.lda + k0 + a_lane_off;
             const int i = lane >> 2;
             const int kq = (lane & 3) ^ ((i >> 2) & 3);
@@ -229,7 +233,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
             gk = gk <= a.lda - 4 ? gk : a.lda - 4;
             return Af + pl * pa + (size_t)grow * a.lda + gk;
         }
-        const int q = NW * (d - DA) + wave, pl = q / BBLK, blk = q % BBLK;
+        const int pl = q / BBLK, blk = q % BBLK;
         // staged planes: 0..3 = B^[f] (B1r, B1i, B2r, B2i); 4..7 = D, E from
         // B^[g]: Dr = -B2r, Di = B2i, Er = B1r, Ei = -B1i (signs applied later)
         const int src = pl < 4 ? pl : (pl == 4 ? 2 : pl == 5 ? 3 : pl == 6 ? 0 : 1);
@@ -241,13 +245,26 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
         gc = gc <= a.ldb - 4 ? gc : a.ldb - 4;
         return base + (size_t)gk * a.ldb + gc;
     };
+    auto block_dst = [&](int b, bool isA, int q) -> float* {
+        return isA ? &sm.A[b][q / ABLK][q % ABLK][0] : &sm.B[b][q / BBLK][q % BBLK][0];
+    };
+    // slot d of this wave (d is a compile-time constant at every call)
+    auto slot_src = [&](int c, int d, bool fast) -> const float* {
+        return d < DA ? block_src(c, true, NW * d + wave, fast) : block_src(c, false, NW * (d - DA) + wave, fast);
+    };
     auto slot_dst = [&](int b, int d) -> float* {
-        if (d < DA) {
-            const int q = NW * d + wave;
-            return &sm.A[b][q / ABLK][q % ABLK][0];
-        }
-        const int q = NW * (d - DA) + wave;
-        return &sm.B[b][q / BBLK][q % BBLK][0];
+        return d < DA ? block_dst(b, true, NW * d + wave) : block_dst(b, false, NW * (d - DA) + wave);
+    };
+    // whole interior chunk c issued by the NW / 2 waves of plane group 1 alone
+    auto issue_fast_g1 = [&](int c) {
+        constexpr int NG = NW / 2;
+#pragma unroll
+        for (int d = 0; d < 4 * ABLK / NG; ++d)
+            dma16(block_src(c, true, NG * d + tw, true), block_dst(c & 1, true, NG * d + tw));
+#pragma unroll
+        for (int d = 0; d < 8 * BBLK / NG; ++d)
+            dma16(block_src(c, false, NG * d + tw, true), block_dst(c & 1, false, NG * d + tw));
+        __builtin_amdgcn_sched_barrier(0);
     };
 
     // DMA of chunk c into buffer b
@@ -270,8 +287,6 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     };
     auto chunk_inside = [&](int c) { return !edge_tile && (c * KT + KT <= a.n); };
 
-    const int grp = PG ? wave / WG : 0;                  // plane group (wave-uniform)
-    const int tw = PG ? wave % WG : wave;
     const int wm = tw % WM, wn = tw / WM;
     const int lr = lane & 31, lg = lane >> 5;
 
@@ -483,6 +498,13 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     auto compute_pg = [&](auto G, int c, int b, bool mask, bool inter) {
         constexpr int g0 = decltype(G)::value;
         typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        // The DMA of chunk c + 1 is issued by group 1 alone, before its
+        // fragment reads: group 0's reads then meet an idle LDS and its
+        // products start sooner after the barrier (group 0 also wins the
+        // MFMA arbitration, so the pipe fills from the start of the chunk).
+        if constexpr (g0 == 1) {
+            if (inter) issue_fast_g1(c + 1);
+        }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int cl = wn * (NT / 2) + nb * 32 + lr;
@@ -531,10 +553,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 const int qa = 4 * g0 + k, qb = qa + 2;
-                if (inter) {
-#pragma unroll
-                    for (int i4 = 0; i4 < 4; ++i4) issue_slice(c + 1, 4 * k + i4);
-                }
+
                 V8 yh[2], yl[2], nyh[2], nyl[2];
                 bfrag(qa, yh[0], yl[0]);
                 bfrag(qb, yh[1], yl[1]);
