@@ -553,7 +553,6 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 const int qa = 4 * g0 + k, qb = qa + 2;
-
                 V8 yh[2], yl[2], nyh[2], nyl[2];
                 bfrag(qa, yh[0], yl[0]);
                 bfrag(qb, yh[1], yl[1]);
