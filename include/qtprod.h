@@ -215,6 +215,24 @@ int qt_batched_plan_destroy(qt_batched_plan plan);
  * their tile shape too. */
 int qt_autotune(int precision, hipStream_t stream);
 
+/* Workspace bytes needed by qt_tprod_complex (0 if an argument is invalid or
+ * the precision is not QT_FP32 / QT_SPLIT_BF16). */
+size_t qt_complex_workspace_size(int m, int n, int s, int p, int precision);
+
+/* T-product of complex tensors, the special case A2 = B2 = 0 of the
+ * quaternion product (Algorithm 2.1 and Proposition 2.1 of the paper, the
+ * complex case that the quaternion method extends): C^[f] = A^[f] B^[f] for
+ * every frequency, with no coupling to -f, i.e. one complex product per face
+ * instead of four coupled ones, and one complex tube FFT per tensor.  Layout:
+ * TWO planes per tensor, [2][p][rows][cols] = (Re, Im); A: m x n x p,
+ * B: n x s x p, C: m x s x p (device pointers, C fully overwritten).
+ * precision: QT_FP32 (FP32 MFMA) or QT_SPLIT_BF16 (bf16 hi+lo products, as
+ * for qt_tprod); QT_SPLIT_FP16 and QT_FP64 return QT_ERR_UNSUPPORTED.  A real
+ * tensor is a complex one with a zero imaginary plane.  Same preconditions,
+ * ownership and error behaviour as qt_tprod. */
+int qt_tprod_complex(int m, int n, int s, int p, const void* A, const void* B, void* C,
+                     int precision, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Workspace bytes needed by qt_tprod_backward. */
 size_t qt_backward_workspace_size(int m, int n, int s, int p, int precision);
 

@@ -53,6 +53,8 @@ SIGNATURES = {
     "qt_batched_plan_launch": (_I, [_P, _P]),
     "qt_batched_plan_destroy": (_I, [_P]),
     "qt_autotune": (_I, [_I, _P]),
+    "qt_complex_workspace_size": (_SZ, [_I, _I, _I, _I, _I]),
+    "qt_tprod_complex": (_I, [_I, _I, _I, _I, _P, _P, _P, _I, _P, _SZ, _P]),
     "qt_backward_workspace_size": (_SZ, [_I, _I, _I, _I, _I]),
     "qt_tprod_backward": (_I, [_I, _I, _I, _I, _P, _P, _P, _P, _P, _I, _P, _SZ, _P]),
 }
@@ -112,6 +114,14 @@ def qt_tube_fft(rows, cols, p, X, ldx, Xh, ldh, inverse, precision, stream=0) ->
 
 def qt_fourier_tprod(m, n, s, p, Ah, lda, Bh, ldb, Ch, ldc, precision, stream=0) -> int:
     return lib().qt_fourier_tprod(m, n, s, p, Ah, lda, Bh, ldb, Ch, ldc, precision, stream)
+
+
+def qt_complex_workspace_size(m, n, s, p, precision) -> int:
+    return lib().qt_complex_workspace_size(m, n, s, p, precision)
+
+
+def qt_tprod_complex(m, n, s, p, A, B, C, precision, ws, ws_bytes, stream=0) -> int:
+    return lib().qt_tprod_complex(m, n, s, p, A, B, C, precision, ws, ws_bytes, stream)
 
 
 def qt_split_words(rows, cols, p, Xh, ld, stream=0) -> int:

@@ -374,6 +374,54 @@ int qt_tprod(int m, int n, int s, int p, const void* A, const void* B, void* C, 
                             (char*)ws, stream);
 }
 
+// ------------------------------------------------------- complex T-product
+size_t qt_complex_workspace_size(int m, int n, int s, int p, int precision) {
+    if ((precision != QT_FP32 && precision != QT_SPLIT_BF16) || !dims_ok(m, n, p) || !dims_ok(n, s, p) ||
+        !dims_ok(m, s, p))
+        return 0;
+    // two planes per tensor: half of the quaternion Fourier buffers
+    auto half = [](long rows, long cols, long p) {
+        return align_up(2 * (size_t)p * (size_t)rows * (size_t)qt::fourier_ld(cols) * sizeof(float));
+    };
+    return half(m, n, p) + half(n, s, p) + half(m, s, p);
+}
+
+int qt_tprod_complex(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision,
+                     void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (precision != QT_FP32 && precision != QT_SPLIT_BF16) {
+        return valid_precision(precision) ? QT_ERR_UNSUPPORTED : QT_ERR_INVALID_ARG;
+    }
+    if (!dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p)) return QT_ERR_INVALID_ARG;
+    if (!A || !B || !C || !ws) return QT_ERR_INVALID_ARG;
+    if (!aligned16(A) || !aligned16(B) || !aligned16(C) || !aligned16(ws)) return QT_ERR_INVALID_ARG;
+    const size_t need = qt_complex_workspace_size(m, n, s, p, precision);
+    if (ws_bytes < need) return QT_ERR_INVALID_ARG;
+    const size_t ab = tensor_bytes(m, n, p, precision) / 2, bb = tensor_bytes(n, s, p, precision) / 2;
+    const size_t cb = tensor_bytes(m, s, p, precision) / 2;
+    if (overlaps(C, cb, A, ab) || overlaps(C, cb, B, bb) || overlaps(ws, need, A, ab) ||
+        overlaps(ws, need, B, bb) || overlaps(ws, need, C, cb))
+        return QT_ERR_INVALID_ARG;
+    if (!p_supported(p, precision)) return QT_ERR_UNSUPPORTED;
+    Twiddles tw;
+    int st = get_plan(p, stream, &tw);
+    if (st != QT_OK) return st;
+    const int lda = (int)qt::fourier_ld(n), ldb = (int)qt::fourier_ld(s), ldc = ldb;
+    char* w = (char*)ws;
+    float* Ah = reinterpret_cast<float*>(w);
+    float* Bh = reinterpret_cast<float*>(w + align_up(2 * (size_t)p * m * lda * sizeof(float)));
+    float* Ch = reinterpret_cast<float*>(w + align_up(2 * (size_t)p * m * lda * sizeof(float)) +
+                                         align_up(2 * (size_t)p * n * ldb * sizeof(float)));
+    const int pack = precision == QT_SPLIT_BF16 ? 1 : 0;
+    // one CD part (planes 0, 1) per tensor
+    FftJob<float> fwd[2] = {{(const float*)A, Ah, m, n, n, lda, pack, 1}, {(const float*)B, Bh, n, s, s, ldb, pack, 1}};
+    if (qt::launch_tube_fft<float>(p, false, fwd, 2, tw, stream) != hipSuccess) return QT_ERR_HIP;
+    FacewiseArgs<float> fa{Ah, Bh, Ch, m, n, s, p, lda, ldb, ldc};
+    st = hip_status(qt::launch_facewise_cx(fa, precision == QT_SPLIT_BF16 ? 1 : 0, stream));
+    if (st != QT_OK) return st;
+    FftJob<float> inv[1] = {{Ch, (float*)C, m, s, ldc, s, 0, 1}};
+    return hip_status(qt::launch_tube_fft<float>(p, true, inv, 1, tw, stream));
+}
+
 size_t qt_backward_workspace_size(int m, int n, int s, int p, int precision) {
     if (!valid_precision(precision) || !dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p))
         return 0;

@@ -115,7 +115,7 @@ bluestein_kernel(FftJob<T> j0, FftJob<T> j1, int p, int M, int logM, int ntubes,
     const int part = blockIdx.y & 1;
     const long count = (long)jb.rows * jb.cols;
     const long e0 = (long)blockIdx.x * ntubes;
-    if (e0 >= count) return;
+    if (e0 >= count || part >= jb.parts) return;      // whole workgroup
     const int nt = (int)((count - e0) < ntubes ? (count - e0) : ntubes);
     const size_t sface = (size_t)jb.rows * jb.src_ld;
     const size_t dface = (size_t)jb.rows * jb.dst_ld;

@@ -119,6 +119,21 @@ __global__ void __launch_bounds__(256) facewise_f64_valu(FacewiseArgs<double> a)
     }
 }
 
+// ------------------------------------------------------ complex products
+// A2 = B2 = 0 (complex tensors, the paper's Algorithm 2.1 / Proposition 2.1
+// case): C^[f] = A^[f] B^[f] with no coupling, two A planes and two B planes
+// per chunk, so a 256 x 64 tile fits in 80 KB of LDS; 8 waves (4 x 2), each
+// 64 x 32 (four independent accumulator chains).
+constexpr int kCxMT = 256, kCxNT = 64;
+
+template <int MODE>
+__global__ void __launch_bounds__(512) facewise_cx_kernel(FacewiseArgs<float> a, TileGrid tg) {
+    __shared__ __attribute__((aligned(16))) V2Smem<kCxMT, kCxNT, true> sm;
+    int f, tm, tn;
+    if (!tile_of_block(tg, f, tm, tn)) return;
+    tile_v2<MODE, kCxMT, kCxNT, 8, false, true>(a, f, tm * kCxMT, tn * kCxNT, 1.f, 1.f, sm);
+}
+
 // ---------------------------------------------------- narrow products (s <= 4)
 // A block-circulant quaternion matrix times a few tube vectors (s <= 4; the
 // circulant mat-vec of Theorems 4.2 / 4.3 when m = n = s = 1): the coupled
@@ -342,6 +357,16 @@ hipError_t launch_facewise_f32(const FacewiseArgs<float>& a, int precision, hipS
         case TILE_64x64: return launch_cfg<TILE_64x64>(a, precision, scales, stream);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_facewise_cx(const FacewiseArgs<float>& a, int precision, hipStream_t stream) {
+    const int tiles_m = (a.m + kCxMT - 1) / kCxMT, tiles_n = (a.s + kCxNT - 1) / kCxNT;
+    const TileGrid tg{tiles_m, tiles_n, a.p};
+    const dim3 grid((unsigned)(tiles_m * tiles_n * a.p)), block(512);
+    if (precision == 0) hipLaunchKernelGGL(facewise_cx_kernel<0>, grid, block, 0, stream, a, tg);
+    else if (precision == 1) hipLaunchKernelGGL(facewise_cx_kernel<1>, grid, block, 0, stream, a, tg);
+    else return hipErrorNotSupported;
+    return hipGetLastError();
 }
 
 hipError_t launch_facewise_f64(const FacewiseArgs<double>& a, hipStream_t stream) {

@@ -144,10 +144,12 @@ __host__ __device__ constexpr bool plane_groups(int mode, int cfg) { return mode
 //         when the fragments are formed, on v_mfma_f32_32x32x16_f16.
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-template <int MT, int NT>
+// CX: complex products (two A planes, two B planes) instead of the coupled
+// quaternion ones (four A planes, eight staged B planes).
+template <int MT, int NT, bool CX = false>
 struct V2Smem {
-    float A[2][4][MT / 16][256];      // [buffer][plane][16-row block][1 KB]
-    float B[2][8][NT / 16][256];      // [buffer][plane][block of 256/NT k-rows][1 KB]
+    float A[2][CX ? 2 : 4][MT / 16][256];      // [buffer][plane][16-row block][1 KB]
+    float B[2][CX ? 2 : 8][NT / 16][256];      // [buffer][plane][block of 256/NT k-rows][1 KB]
 };
 
 __device__ __forceinline__ void dma16(const float* g, float* lds_block) {
@@ -179,20 +181,23 @@ __device__ __forceinline__ void unpack8(const unsigned (&w)[8], V8& hi, V8& lo) 
     lo = __builtin_bit_cast(V8, l);
 }
 
-template <int MODE, int MT, int NT, int NW = 4, bool PG = false>
+template <int MODE, int MT, int NT, int NW = 4, bool PG = false, bool CX = false>
 __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int m0, int n0,
-                                        float sa, float sb, V2Smem<MT, NT>& sm) {
+                                        float sa, float sb, V2Smem<MT, NT, CX>& sm) {
     using H = typename std::conditional<MODE == 2, _Float16, __bf16>::type;
     using V8 = typename SplitTypes<H>::v8;
     // NW waves as a (NW / 2) x 2 grid; each wave owns MB x NB 32 x 32 blocks.
     // PG (split bf16): two plane groups of NW / 2 waves, each a (NW / 4) x 2
     // grid over the whole tile; group 0 takes the B^[f] planes with A1, group
     // 1 the D, E planes with A2, and the partial sums meet once per tile.
-    static_assert(!PG || MODE == 1, "plane groups are built for the split-bf16 path");
+    // CX: the complex product C^[f] = A^[f] B^[f] (A2 = B2 = 0: no coupling
+    // with -f), two A planes, two B planes, output planes 0 and 1.
+    static_assert(!PG || (MODE == 1 && !CX), "plane groups are built for the split-bf16 quaternion path");
+    constexpr int NPA = CX ? 2 : 4, NPB = CX ? 2 : 8;
     constexpr int WG = PG ? NW / 2 : NW;
     constexpr int WM = WG / 2;
     constexpr int MB = MT / (32 * WM), NB = NT / 64;
-    static_assert(MB >= 1 && MT == 32 * WM * MB && (4 * (MT / 16)) % NW == 0 && (8 * (NT / 16)) % NW == 0,
+    static_assert(MB >= 1 && MT == 32 * WM * MB && (NPA * (MT / 16)) % NW == 0 && (NPB * (NT / 16)) % NW == 0,
                   "tile shape does not fit the wave grid");
     constexpr int ABLK = MT / 16, BBLK = NT / 16;       // 1 KB blocks per plane
     constexpr int RB = 256 / NT, CQ = NT / 4;           // B block: RB k-rows of CQ 16-byte pieces
@@ -214,7 +219,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     // the rest B blocks.  Interior chunks ("fast") use a wave-uniform base plus
     // a per-lane offset fixed for the tile; other chunks clamp rows, columns
     // and k to valid addresses (the compute masks those entries).
-    constexpr int DA = 4 * ABLK / NW, DB = 8 * BBLK / NW, DTOT = DA + DB;   // slots per wave per chunk
+    constexpr int DA = NPA * ABLK / NW, DB = NPB * BBLK / NW, DTOT = DA + DB;   // slots per wave per chunk
     const int a_i = lane >> 2;
     const int a_lane_off = a_i * a.lda + 4 * ((lane & 3) ^ ((a_i >> 2) & 3));
     const int b_lane_off = (lane / CQ) * a.ldb + 4 * (lane % CQ);
@@ -259,10 +264,10 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     auto issue_fast_g1 = [&](int c) {
         constexpr int NG = NW / 2;
 #pragma unroll
-        for (int d = 0; d < 4 * ABLK / NG; ++d)
+        for (int d = 0; d < NPA * ABLK / NG; ++d)
             dma16(block_src(c, true, NG * d + tw, true), block_dst(c & 1, true, NG * d + tw));
 #pragma unroll
-        for (int d = 0; d < 8 * BBLK / NG; ++d)
+        for (int d = 0; d < NPB * BBLK / NG; ++d)
             dma16(block_src(c, false, NG * d + tw, true), block_dst(c & 1, false, NG * d + tw));
         __builtin_amdgcn_sched_barrier(0);
     };
@@ -308,7 +313,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
         const int s1 = 4 * i + ((2 * lg + 1) ^ ((i >> 2) & 3));
         const bool row_ok = !mask || (m0 + rl < a.m);
 #pragma unroll
-        for (int pl = 0; pl < 4; ++pl) {
+        for (int pl = 0; pl < NPA; ++pl) {
             const float4 u = *reinterpret_cast<const float4*>(&sm.A[b][pl][blk][4 * s0]);
             const float4 w = *reinterpret_cast<const float4*>(&sm.A[b][pl][blk][4 * s1]);
             const float v[8] = {u.x, u.y, u.z, u.w, w.x, w.y, w.z, w.w};
@@ -329,7 +334,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
         const int s1 = 4 * i + ((2 * lg + 1) ^ ((i >> 2) & 3));
         const bool row_ok = !mask || (m0 + rl < a.m);
 #pragma unroll
-        for (int pl = 0; pl < 4; ++pl) {
+        for (int pl = 0; pl < NPA; ++pl) {
             const u4 u = *reinterpret_cast<const u4*>(&sm.A[b][pl][blk][4 * s0]);
             const u4 v = *reinterpret_cast<const u4*>(&sm.A[b][pl][blk][4 * s1]);
             const unsigned x[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
@@ -366,8 +371,11 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb) load_a(b, mb, c, mask, xa[mb]);
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    if (inter) issue_slice(c + 1, q);
+                for (int q = 0; q < NPB; ++q) {
+                    if (inter) {
+#pragma unroll
+                        for (int sl = q * 8 / NPB; sl < (q + 1) * 8 / NPB; ++sl) issue_slice(c + 1, sl);
+                    }
                     const float sgn = (q == 4 || q == 7) ? -1.f : 1.f;
                     float y[8], ny[8];
 #pragma unroll
@@ -402,12 +410,12 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                         unsigned wa[4][8];
                         load_a_words(b, mb, c, mask, wa);
 #pragma unroll
-                        for (int pl = 0; pl < 4; ++pl) unpack8(wa[pl], ah[mb][pl], al[mb][pl]);
+                        for (int pl = 0; pl < NPA; ++pl) unpack8(wa[pl], ah[mb][pl], al[mb][pl]);
                     } else {
                         float xa[4][8];
                         load_a(b, mb, c, mask, xa);
 #pragma unroll
-                        for (int pl = 0; pl < 4; ++pl) split8<H>(xa[pl], ah[mb][pl], al[mb][pl]);
+                        for (int pl = 0; pl < NPA; ++pl) split8<H>(xa[pl], ah[mb][pl], al[mb][pl]);
                     }
                 }
                 // all B words of the chunk are read up front, so that their LDS
@@ -415,7 +423,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                 unsigned wb[8][8];
                 if constexpr (MODE == 1) {
 #pragma unroll
-                    for (int q = 0; q < 8; ++q)
+                    for (int q = 0; q < NPB; ++q)
 #pragma unroll
                         for (int j = 0; j < 8; ++j) {
                             const int k = 8 * lg + j;
@@ -446,6 +454,38 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                         split8<H>(x, yh, yl);
                     }
                 };
+                if constexpr (CX) {
+                    // complex: plane 0 (Re B) and plane 1 (Im B) of C1 alone
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        if (inter) {
+#pragma unroll
+                            for (int sl = 4 * q; sl < 4 * q + 4; ++sl) issue_slice(c + 1, sl);
+                        }
+                        V8 yh, yl, nyh, nyl;
+                        bfrag(q, yh, yl);
+                        if (q == 1) {
+                            nyh = neg8(yh);
+                            nyl = neg8(yl);
+                        }
+#pragma unroll
+                        for (int step = 0; step < 3; ++step)
+#pragma unroll
+                            for (int mb = 0; mb < MB; ++mb) {
+                                const V8 xr = step == 0 ? al[mb][0] : ah[mb][0];
+                                const V8 xi = step == 0 ? al[mb][1] : ah[mb][1];
+                                const V8 y = step == 1 ? yl : yh;
+                                if (q == 0) {          // Re += Ar Br, Im += Ai Br
+                                    acc[0][mb][nb] = mfma16<H>(xr, y, acc[0][mb][nb]);
+                                    acc[1][mb][nb] = mfma16<H>(xi, y, acc[1][mb][nb]);
+                                } else {               // Re -= Ai Bi, Im += Ar Bi
+                                    const V8 ny = step == 1 ? nyl : nyh;
+                                    acc[0][mb][nb] = mfma16<H>(xi, ny, acc[0][mb][nb]);
+                                    acc[1][mb][nb] = mfma16<H>(xr, y, acc[1][mb][nb]);
+                                }
+                            }
+                    }
+                } else {
                 // Planes are taken in pairs (q, q + 2) = (0, 2), (1, 3), (4, 6),
                 // (5, 7): the first feeds C1, the second C2, so each of the three
                 // split products runs over 4 MB independent accumulator chains.
@@ -489,6 +529,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                                 }
                             }
                 }
+                }   // !CX
             }
         }
     };
@@ -662,7 +703,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
             __syncthreads();                 // LDS may be reused by the next tile
             store_tile<MB, NB, keep, 2>(a, f, row0, col0, acc, scale, lane);
         } else {
-            store_tile<MB, NB>(a, f, row0, col0, acc, scale, lane);
+            store_tile<MB, NB, 0, CX ? 2 : 4>(a, f, row0, col0, acc, scale, lane);
         }
     };
     if constexpr (PG) {

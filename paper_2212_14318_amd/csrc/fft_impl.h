@@ -198,7 +198,7 @@ tube_fft_kernel(FftJobs2<T> jobs, const typename Vec2<T>::type* __restrict__ tw)
     const int part = blockIdx.y & 1;                 // 0: X1 (planes 0,1), 1: X2 (planes 2,3)
     const FftJob<T> jb = jobs.j[job];
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (long)jb.rows * jb.cols) return;
+    if (e >= (long)jb.rows * jb.cols || part >= jb.parts) return;
     tube_fft_one<P, INV, T>(jb, part, e, tw);
 }
 

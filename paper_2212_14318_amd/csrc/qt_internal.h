@@ -27,6 +27,7 @@ struct FftJob {
     T* dst;
     int rows, cols, src_ld, dst_ld;
     int pack;
+    int parts = 2;            // CD parts to transform: 2 (quaternion) or 1 (complex, planes 0 and 1)
 };
 
 // Bluestein tables of one p (lengths without a register-resident kernel):
@@ -92,6 +93,9 @@ constexpr int kNarrowMaxS = 4;
 hipError_t launch_facewise_f32(const FacewiseArgs<float>& a, int precision, hipStream_t stream,
                                int tile_cfg = 0, const float* scales = nullptr);
 hipError_t launch_facewise_f64(const FacewiseArgs<double>& a, hipStream_t stream);
+// Complex products C^[f] = A^[f] B^[f] (planes 0, 1 of each tensor; no -f
+// coupling).  precision: 0 = FP32 MFMA, 1 = split bf16 (operand words).
+hipError_t launch_facewise_cx(const FacewiseArgs<float>& a, int precision, hipStream_t stream);
 
 // fp16 split: per-frequency power-of-two scales of A^ and of the B^ pairs
 // {f, -f} into scales[0 .. 2p); partials needs p * (fp16_partial_blocks(m, n) +

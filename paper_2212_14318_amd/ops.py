@@ -25,9 +25,9 @@ def _dtype(prec: int):
     return torch.float64 if prec == nat.QT_FP64 else torch.float32
 
 
-def _check_tensor(x: torch.Tensor, name: str, prec: int):
-    if not isinstance(x, torch.Tensor) or x.dim() != 4 or x.shape[0] != 4:
-        raise ValueError(f"{name} must be a tensor of shape (4, p, rows, cols)")
+def _check_tensor(x: torch.Tensor, name: str, prec: int, planes: int = 4):
+    if not isinstance(x, torch.Tensor) or x.dim() != 4 or x.shape[0] != planes:
+        raise ValueError(f"{name} must be a tensor of shape ({planes}, p, rows, cols)")
     if x.device.type != "cuda":
         raise ValueError(f"{name} must live on a ROCm device")
     if x.dtype != _dtype(prec):
@@ -119,6 +119,30 @@ def tprod(A: torch.Tensor, B: torch.Tensor, precision="fp32", out: torch.Tensor 
     st = nat.qt_tprod(m, n, s, p, A.data_ptr(), B.data_ptr(), out.data_ptr(), prec,
                       ws.data_ptr(), ws.numel(), _stream(A.device))
     nat.check(st, "qt_tprod")
+    return out
+
+
+def tprod_complex(A: torch.Tensor, B: torch.Tensor, precision="fp32", out: torch.Tensor | None = None,
+                  ws: torch.Tensor | None = None) -> torch.Tensor:
+    """C = A * B for complex tensors of shape (2, p, rows, cols) = (Re, Im):
+    one uncoupled complex product per frequency ("fp32" or "split_bf16")."""
+    prec = _prec(precision)
+    _check_tensor(A, "A", nat.QT_FP32, planes=2)
+    _check_tensor(B, "B", nat.QT_FP32, planes=2)
+    _, p, m, n = A.shape
+    if B.shape[1] != p or B.shape[2] != n:
+        raise ValueError("B must be n x s x p with A m x n x p")
+    s = B.shape[3]
+    if out is None:
+        out = torch.empty((2, p, m, s), dtype=A.dtype, device=A.device)
+    else:
+        _check_tensor(out, "out", nat.QT_FP32, planes=2)
+    need = nat.qt_complex_workspace_size(m, n, s, p, prec)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, A.device)
+    st = nat.qt_tprod_complex(m, n, s, p, A.data_ptr(), B.data_ptr(), out.data_ptr(), prec,
+                              ws.data_ptr(), ws.numel(), _stream(A.device))
+    nat.check(st, "qt_tprod_complex")
     return out
 
 

@@ -121,6 +121,28 @@ def test_fourier_tprod_rejects_bad_args():
     assert nat.qt_fourier_ld(5) == 8 and nat.qt_fourier_ld(8) == 8 and nat.qt_fourier_ld(0) == 0
 
 
+@pytest.mark.parametrize("m,n,s,p", [(1, 1, 1, 1), (17, 5, 33, 7), (256, 256, 256, 64)])
+def test_complex_workspace_formula(m, n, s, p):
+    half = lambda r, c: (2 * p * r * ((c + 3) // 4 * 4) * 4 + 255) // 256 * 256
+    want = half(m, n) + half(n, s) + half(m, s)
+    for prec in (nat.QT_FP32, nat.QT_SPLIT_BF16):
+        assert nat.qt_complex_workspace_size(m, n, s, p, prec) == want
+    assert nat.qt_complex_workspace_size(m, n, s, p, nat.QT_FP64) == 0
+
+
+def test_complex_rejects_bad_args():
+    buf = ctypes.c_void_p(1 << 20)       # never dereferenced: rejected before any launch
+    ws_n = nat.qt_complex_workspace_size(4, 4, 4, 4, nat.QT_FP32)
+    assert nat.qt_tprod_complex(0, 4, 4, 4, buf, buf, buf, nat.QT_FP32, buf, ws_n, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_complex(4, 4, 4, 4, None, buf, buf, nat.QT_FP32, buf, ws_n, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_complex(4, 4, 4, 4, buf, buf, buf, nat.QT_FP64, buf, ws_n, None) == nat.QT_ERR_UNSUPPORTED
+    assert nat.qt_tprod_complex(4, 4, 4, 4, buf, buf, buf, 9, buf, ws_n, None) == nat.QT_ERR_INVALID_ARG
+    a, b, c = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20), ctypes.c_void_p(3 << 20)
+    w = ctypes.c_void_p(4 << 20)
+    assert nat.qt_tprod_complex(4, 4, 4, 4, a, b, c, nat.QT_FP32, w, ws_n - 1, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_complex(4, 4, 4, 4, a, b, a, nat.QT_FP32, w, ws_n, None) == nat.QT_ERR_INVALID_ARG
+
+
 def test_split_words_rejects_bad_args():
     buf = ctypes.c_void_p(4096)          # never dereferenced: rejected before any launch
     assert nat.qt_split_words(0, 4, 4, buf, 4, None) == nat.QT_ERR_INVALID_ARG
