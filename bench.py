@@ -41,6 +41,8 @@ WORKLOADS = {
                                 "N(0,1) (seeds 6000/6001), coupled product on resident Fourier operands"),
     "complex": dict(cfg=3, desc="complex A, B 1024x1024x32 (planes Re, Im of the quaternion N(0,1) inputs, "
                                 "seeds 3000/3001): one uncoupled complex product per frequency"),
+    "real": dict(cfg=3, desc="real A, B 1024x1024x32 (plane 0 of the quaternion N(0,1) inputs, seeds 3000/3001): "
+                          "Hermitian half spectrum, 17 complex products"),
     "chain": dict(cfg=3, desc="chain (A * B) * C, A, B, C 1024x1024x32 quaternion, N(0,1) "
                               "(seeds 3000/3001/3002), kept in the Fourier domain between the products"),
 }
@@ -142,8 +144,8 @@ def main():
         return bench_chain(args, wl, dev, stream)
     if args.workload == "matvec":
         return bench_matvec(args, wl, dev, stream)
-    if args.workload == "complex":
-        return bench_complex(args, wl, dev, stream)
+    if args.workload in ("complex", "real"):
+        return bench_complex(args, wl, dev, stream, real=args.workload == "real")
     t0 = time.time()
     inputs = synth.config_inputs(cfg)
     A64, B64 = inputs[0], inputs[1]
@@ -462,39 +464,45 @@ def bench_chain(args, wl, dev, stream):
            "per_precision": res, "roofline": None, "cpu_baseline": None})
 
 
-def bench_complex(args, wl, dev, stream):
+def bench_complex(args, wl, dev, stream, real=False):
     """Complex T-product (second Cayley-Dickson half zero): two-plane tube
-    FFTs and 8 m n s p flops of uncoupled complex products, against the
-    quaternion path on the same tensors embedded with zero j-parts.  Sampled
-    entries are checked against the oracle's definition."""
+    FFTs and 8 m n s p flops of uncoupled complex products.  Real T-product
+    (one plane): Hermitian half spectrum, 8 m n s (p/2 + 1) flops.  Timed
+    against the quaternion path on the same tensors embedded with zero
+    planes; sampled entries are checked against the oracle's definition."""
     import numpy as np
     import torch
 
     import oracle
     import synth
     from paper_2212_14318_amd import _native as nat
-    from paper_2212_14318_amd import tprod, tprod_complex
+    from paper_2212_14318_amd import tprod, tprod_complex, tprod_real
 
-    A64, B64 = (x[:2].copy() for x in synth.config_inputs(3)[:2])
+    planes = 1 if real else 2
+    A64, B64 = (x[:planes].copy() for x in synth.config_inputs(3)[:2])
     _, p, m, n = A64.shape
     s = B64.shape[3]
     A, B = (torch.from_numpy(x).to(dev, torch.float32) for x in (A64, B64))
-    Aq, Bq = (torch.cat([x, torch.zeros_like(x)]) for x in (A, B))
-    C = torch.empty((2, p, m, s), device=dev)
+    Aq, Bq = (torch.cat([x, torch.zeros((4 - planes,) + x.shape[1:], device=dev)]) for x in (A, B))
+    C = torch.empty((planes, p, m, s), device=dev)
     Cq = torch.empty((4, p, m, s), device=dev)
-    F = 8.0 * m * n * s * p
+    F = 8.0 * m * n * s * ((p // 2 + 1) if real else p)
     rng = np.random.Generator(np.random.PCG64(7))
     kk, ii, jj = rng.integers(0, p, 64), rng.integers(0, m, 64), rng.integers(0, s, 64)
-    Aq64, Bq64 = (np.concatenate([x, np.zeros_like(x)]) for x in (A64, B64))
-    ref = oracle.tprod_entries(Aq64, Bq64, kk, ii, jj)[:2]
+    Aq64, Bq64 = (np.concatenate([x, np.zeros((4 - planes,) + x.shape[1:])]) for x in (A64, B64))
+    ref = oracle.tprod_entries(Aq64, Bq64, kk, ii, jj)[:planes]
     res = {}
     precs = [x for x in args.precisions.split(",") if x]
     for prec in precs:
-        ws = torch.empty(nat.qt_complex_workspace_size(m, n, s, p, nat.PRECISIONS[prec]), dtype=torch.uint8,
-                         device=dev)
+        wsz = (nat.qt_real_workspace_size if real else nat.qt_complex_workspace_size)(m, n, s, p,
+                                                                                     nat.PRECISIONS[prec])
+        ws = torch.empty(wsz, dtype=torch.uint8, device=dev)
+        if real:
+            run = lambda: tprod_real(A[0], B[0], prec, out=C[0], ws=ws)
+        else:
+            run = lambda: tprod_complex(A, B, prec, out=C, ws=ws)
         times = {}
-        for name, fn in (("complex", lambda: tprod_complex(A, B, prec, out=C, ws=ws)),
-                         ("quaternion", lambda: tprod(Aq, Bq, prec, out=Cq))):
+        for name, fn in (("complex", run), ("quaternion", lambda: tprod(Aq, Bq, prec, out=Cq))):
             for _ in range(args.warmup):
                 fn()
             torch.cuda.synchronize()
@@ -507,8 +515,9 @@ def bench_complex(args, wl, dev, stream):
         err = float(np.sqrt(np.sum((got - ref) ** 2)) / np.sqrt(np.sum(ref ** 2)))
         res[prec] = {"ms_per_step": times["complex"], "quaternion_path_ms": times["quaternion"],
                      "tflops": F / (times["complex"] * 1e-3) / 1e12, "sampled_rel_err": err}
-        log(f"[bench] complex {prec}: {times['complex']:.3f} ms ({res[prec]['tflops']:.1f} TFLOP/s), "
-            f"quaternion path on zero j-parts {times['quaternion']:.3f} ms, sampled rel err {err:.2e}")
+        log(f"[bench] {'real' if real else 'complex'} {prec}: {times['complex']:.3f} ms "
+            f"({res[prec]['tflops']:.1f} TFLOP/s), quaternion path on zero planes {times['quaternion']:.3f} ms, "
+            f"sampled rel err {err:.2e}")
     head = precs[0]
     _emit({"metric": "T-product TFLOP/s-equiv & % roofline, split-BF16 vs FP32 at stated rel. error",
            "value": round(res[head]["tflops"], 3), "unit": "TFLOP/s", "n_gpus": 1,

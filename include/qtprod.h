@@ -233,6 +233,22 @@ size_t qt_complex_workspace_size(int m, int n, int s, int p, int precision);
 int qt_tprod_complex(int m, int n, int s, int p, const void* A, const void* B, void* C,
                      int precision, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Workspace bytes needed by qt_tprod_real (0 if an argument is invalid or the
+ * precision is not QT_FP32 / QT_SPLIT_BF16). */
+size_t qt_real_workspace_size(int m, int n, int s, int p, int precision);
+
+/* T-product of real tensors (Algorithm 2.1 of the paper on real input, the
+ * T-product of Kilmer and Martin).  The DFT of a real tube is Hermitian,
+ * X^[p - f] = conj(X^[f]), so only frequencies f = 0 .. p/2 are transformed,
+ * multiplied (one complex product C^[f] = A^[f] B^[f] each) and inverted:
+ * p/2 + 1 complex products instead of p.  Layout: ONE plane per tensor,
+ * [p][rows][cols] row-major faces; A: m x n x p, B: n x s x p, C: m x s x p
+ * (device pointers, C fully overwritten).  precision: QT_FP32 or
+ * QT_SPLIT_BF16; QT_SPLIT_FP16 and QT_FP64 return QT_ERR_UNSUPPORTED.  Same
+ * preconditions, ownership and error behaviour as qt_tprod. */
+int qt_tprod_real(int m, int n, int s, int p, const void* A, const void* B, void* C,
+                  int precision, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Workspace bytes needed by qt_tprod_backward. */
 size_t qt_backward_workspace_size(int m, int n, int s, int p, int precision);
 

@@ -13,7 +13,7 @@ Cayley-Dickson parts X1 = a + b i and X2 = c + d i.
     C = qtprod(A, B)                      # differentiable (autograd.Function)
 """
 from .ops import (BatchedPlan, QTProd, autotune, fourier_tprod, qtprod, split_words, tprod,  # noqa: F401
-                  tprod_backward, tprod_batched, tprod_complex, tube_fft)
+                  tprod_backward, tprod_batched, tprod_complex, tprod_real, tube_fft)
 from ._native import PRECISIONS, QtError  # noqa: F401
 
-__all__ = ["tprod", "tprod_complex", "tube_fft", "fourier_tprod", "split_words", "BatchedPlan", "autotune", "tprod_backward", "tprod_batched", "qtprod", "QTProd", "PRECISIONS", "QtError"]
+__all__ = ["tprod", "tprod_complex", "tprod_real", "tube_fft", "fourier_tprod", "split_words", "BatchedPlan", "autotune", "tprod_backward", "tprod_batched", "qtprod", "QTProd", "PRECISIONS", "QtError"]

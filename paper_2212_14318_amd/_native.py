@@ -55,6 +55,8 @@ SIGNATURES = {
     "qt_autotune": (_I, [_I, _P]),
     "qt_complex_workspace_size": (_SZ, [_I, _I, _I, _I, _I]),
     "qt_tprod_complex": (_I, [_I, _I, _I, _I, _P, _P, _P, _I, _P, _SZ, _P]),
+    "qt_real_workspace_size": (_SZ, [_I, _I, _I, _I, _I]),
+    "qt_tprod_real": (_I, [_I, _I, _I, _I, _P, _P, _P, _I, _P, _SZ, _P]),
     "qt_backward_workspace_size": (_SZ, [_I, _I, _I, _I, _I]),
     "qt_tprod_backward": (_I, [_I, _I, _I, _I, _P, _P, _P, _P, _P, _I, _P, _SZ, _P]),
 }
@@ -122,6 +124,14 @@ def qt_complex_workspace_size(m, n, s, p, precision) -> int:
 
 def qt_tprod_complex(m, n, s, p, A, B, C, precision, ws, ws_bytes, stream=0) -> int:
     return lib().qt_tprod_complex(m, n, s, p, A, B, C, precision, ws, ws_bytes, stream)
+
+
+def qt_real_workspace_size(m, n, s, p, precision) -> int:
+    return lib().qt_real_workspace_size(m, n, s, p, precision)
+
+
+def qt_tprod_real(m, n, s, p, A, B, C, precision, ws, ws_bytes, stream=0) -> int:
+    return lib().qt_tprod_real(m, n, s, p, A, B, C, precision, ws, ws_bytes, stream)
 
 
 def qt_split_words(rows, cols, p, Xh, ld, stream=0) -> int:

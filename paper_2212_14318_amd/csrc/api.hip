@@ -374,30 +374,41 @@ int qt_tprod(int m, int n, int s, int p, const void* A, const void* B, void* C, 
                             (char*)ws, stream);
 }
 
-// ------------------------------------------------------- complex T-product
-size_t qt_complex_workspace_size(int m, int n, int s, int p, int precision) {
+// ------------------------------------------- complex and real T-products
+namespace {
+
+// Fourier-side faces: p for complex tensors, p / 2 + 1 for real ones (the
+// spectrum of a real tube is Hermitian).
+int cx_faces(int p, bool real) { return real ? p / 2 + 1 : p; }
+
+size_t cx_workspace(int m, int n, int s, int p, int precision, bool real) {
     if ((precision != QT_FP32 && precision != QT_SPLIT_BF16) || !dims_ok(m, n, p) || !dims_ok(n, s, p) ||
         !dims_ok(m, s, p))
         return 0;
-    // two planes per tensor: half of the quaternion Fourier buffers
-    auto half = [](long rows, long cols, long p) {
-        return align_up(2 * (size_t)p * (size_t)rows * (size_t)qt::fourier_ld(cols) * sizeof(float));
+    const long h = cx_faces(p, real);
+    // two planes (Re, Im) of h faces per tensor
+    auto part = [h](long rows, long cols) {
+        return align_up(2 * (size_t)h * (size_t)rows * (size_t)qt::fourier_ld(cols) * sizeof(float));
     };
-    return half(m, n, p) + half(n, s, p) + half(m, s, p);
+    return part(m, n) + part(n, s) + part(m, s);
 }
 
-int qt_tprod_complex(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision,
-                     void* ws, size_t ws_bytes, hipStream_t stream) {
+// Forward transforms of A and B (two planes, or one real plane to a half
+// spectrum), the uncoupled per-frequency complex products, and the inverse.
+int run_cx(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision, void* ws,
+           size_t ws_bytes, bool real, hipStream_t stream) {
     if (precision != QT_FP32 && precision != QT_SPLIT_BF16) {
         return valid_precision(precision) ? QT_ERR_UNSUPPORTED : QT_ERR_INVALID_ARG;
     }
     if (!dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p)) return QT_ERR_INVALID_ARG;
     if (!A || !B || !C || !ws) return QT_ERR_INVALID_ARG;
     if (!aligned16(A) || !aligned16(B) || !aligned16(C) || !aligned16(ws)) return QT_ERR_INVALID_ARG;
-    const size_t need = qt_complex_workspace_size(m, n, s, p, precision);
+    const size_t need = cx_workspace(m, n, s, p, precision, real);
     if (ws_bytes < need) return QT_ERR_INVALID_ARG;
-    const size_t ab = tensor_bytes(m, n, p, precision) / 2, bb = tensor_bytes(n, s, p, precision) / 2;
-    const size_t cb = tensor_bytes(m, s, p, precision) / 2;
+    const int planes = real ? 1 : 2;
+    const size_t ab = tensor_bytes(m, n, p, precision) / 4 * planes;
+    const size_t bb = tensor_bytes(n, s, p, precision) / 4 * planes;
+    const size_t cb = tensor_bytes(m, s, p, precision) / 4 * planes;
     if (overlaps(C, cb, A, ab) || overlaps(C, cb, B, bb) || overlaps(ws, need, A, ab) ||
         overlaps(ws, need, B, bb) || overlaps(ws, need, C, cb))
         return QT_ERR_INVALID_ARG;
@@ -405,21 +416,45 @@ int qt_tprod_complex(int m, int n, int s, int p, const void* A, const void* B, v
     Twiddles tw;
     int st = get_plan(p, stream, &tw);
     if (st != QT_OK) return st;
+    const int h = cx_faces(p, real);
     const int lda = (int)qt::fourier_ld(n), ldb = (int)qt::fourier_ld(s), ldc = ldb;
     char* w = (char*)ws;
+    const size_t a_bytes = align_up(2 * (size_t)h * m * lda * sizeof(float));
+    const size_t b_bytes = align_up(2 * (size_t)h * n * ldb * sizeof(float));
     float* Ah = reinterpret_cast<float*>(w);
-    float* Bh = reinterpret_cast<float*>(w + align_up(2 * (size_t)p * m * lda * sizeof(float)));
-    float* Ch = reinterpret_cast<float*>(w + align_up(2 * (size_t)p * m * lda * sizeof(float)) +
-                                         align_up(2 * (size_t)p * n * ldb * sizeof(float)));
+    float* Bh = reinterpret_cast<float*>(w + a_bytes);
+    float* Ch = reinterpret_cast<float*>(w + a_bytes + b_bytes);
     const int pack = precision == QT_SPLIT_BF16 ? 1 : 0;
+    const int hf = real ? 1 : 0;
     // one CD part (planes 0, 1) per tensor
-    FftJob<float> fwd[2] = {{(const float*)A, Ah, m, n, n, lda, pack, 1}, {(const float*)B, Bh, n, s, s, ldb, pack, 1}};
+    FftJob<float> fwd[2] = {{(const float*)A, Ah, m, n, n, lda, pack, 1, hf},
+                            {(const float*)B, Bh, n, s, s, ldb, pack, 1, hf}};
     if (qt::launch_tube_fft<float>(p, false, fwd, 2, tw, stream) != hipSuccess) return QT_ERR_HIP;
-    FacewiseArgs<float> fa{Ah, Bh, Ch, m, n, s, p, lda, ldb, ldc};
+    FacewiseArgs<float> fa{Ah, Bh, Ch, m, n, s, h, lda, ldb, ldc};
     st = hip_status(qt::launch_facewise_cx(fa, precision == QT_SPLIT_BF16 ? 1 : 0, stream));
     if (st != QT_OK) return st;
-    FftJob<float> inv[1] = {{Ch, (float*)C, m, s, ldc, s, 0, 1}};
+    FftJob<float> inv[1] = {{Ch, (float*)C, m, s, ldc, s, 0, 1, hf}};
     return hip_status(qt::launch_tube_fft<float>(p, true, inv, 1, tw, stream));
+}
+
+}  // namespace
+
+size_t qt_complex_workspace_size(int m, int n, int s, int p, int precision) {
+    return cx_workspace(m, n, s, p, precision, false);
+}
+
+int qt_tprod_complex(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision,
+                     void* ws, size_t ws_bytes, hipStream_t stream) {
+    return run_cx(m, n, s, p, A, B, C, precision, ws, ws_bytes, false, stream);
+}
+
+size_t qt_real_workspace_size(int m, int n, int s, int p, int precision) {
+    return cx_workspace(m, n, s, p, precision, true);
+}
+
+int qt_tprod_real(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision,
+                  void* ws, size_t ws_bytes, hipStream_t stream) {
+    return run_cx(m, n, s, p, A, B, C, precision, ws, ws_bytes, true, stream);
 }
 
 size_t qt_backward_workspace_size(int m, int n, int s, int p, int precision) {

@@ -119,6 +119,11 @@ bluestein_kernel(FftJob<T> j0, FftJob<T> j1, int p, int M, int logM, int ntubes,
     const int nt = (int)((count - e0) < ntubes ? (count - e0) : ntubes);
     const size_t sface = (size_t)jb.rows * jb.src_ld;
     const size_t dface = (size_t)jb.rows * jb.dst_ld;
+    // Hermitian half spectrum (real tubes): H faces per plane on the Fourier side
+    const int H = p / 2 + 1;
+    const bool half = jb.half != 0;
+    const size_t splane = (size_t)(half && INV ? H : p) * sface;
+    const size_t dplane = (size_t)(half && !INV ? H : p) * dface;
 
     // zero the padded tubes, then load a_k = x_k conj(c_k) (c_k for INV) at rev(k)
     for (int idx = threadIdx.x; idx < ntubes * (M + 1); idx += blockDim.x) buf[idx] = V{0, 0};
@@ -127,8 +132,17 @@ bluestein_kernel(FftJob<T> j0, FftJob<T> j1, int p, int M, int logM, int ntubes,
         const int k = idx / nt, t = idx - k * nt;
         const long e = e0 + t;
         const int i = (int)(e / jb.cols), c = (int)(e - (long)i * jb.cols);
-        const T* sre = jb.src + (size_t)(2 * part) * p * sface + (size_t)k * sface + (size_t)i * jb.src_ld + c;
-        const V x = V{sre[0], sre[(size_t)p * sface]};
+        V x;
+        if (!half) {
+            const T* sre = jb.src + (size_t)(2 * part) * splane + (size_t)k * sface + (size_t)i * jb.src_ld + c;
+            x = V{sre[0], sre[splane]};
+        } else if (!INV) {
+            x = V{jb.src[(size_t)k * sface + (size_t)i * jb.src_ld + c], T(0)};
+        } else {
+            const int kk = k < H ? k : p - k;           // X^[k] = conj(X^[p - k]) for k >= H
+            const T* sre = jb.src + (size_t)kk * sface + (size_t)i * jb.src_ld + c;
+            x = V{sre[0], k < H ? sre[splane] : -sre[splane]};
+        }
         const V ck = INV ? chirp[k] : conjv(chirp[k]);
         buf[(size_t)t * (M + 1) + bitrev((unsigned)k, logM)] = cmulv(x, ck);
     }
@@ -155,14 +169,19 @@ bluestein_kernel(FftJob<T> j0, FftJob<T> j1, int p, int M, int logM, int ntubes,
     lds_fft(buf, nt, M, logM, twm, true);
     // X_f = conj(c_f) y_f / M  (c_f y_f / (M p) for the inverse)
     const T scale = INV ? T(1) / (T(M) * T(p)) : T(1) / T(M);
-    for (int idx = threadIdx.x; idx < p * nt; idx += blockDim.x) {
+    const int nout = half && !INV ? H : p;
+    for (int idx = threadIdx.x; idx < nout * nt; idx += blockDim.x) {
         const int f = idx / nt, t = idx - f * nt;
         const long e = e0 + t;
         const int i = (int)(e / jb.cols), c = (int)(e - (long)i * jb.cols);
         const V cf = INV ? chirp[f] : conjv(chirp[f]);
         const V y = cmulv(buf[(size_t)t * (M + 1) + f], cf);
-        T* dre = jb.dst + (size_t)(2 * part) * p * dface + (size_t)f * dface + (size_t)i * jb.dst_ld + c;
+        T* dre = jb.dst + (size_t)(2 * part) * dplane + (size_t)f * dface + (size_t)i * jb.dst_ld + c;
         const T yr = y.x * scale, yi = y.y * scale;
+        if (half && INV) {                              // real output: one plane
+            dre[0] = yr;
+            continue;
+        }
         if constexpr (!INV && sizeof(T) == 4) {
             if (jb.pack) {
                 auto word = [](float x) {
@@ -172,12 +191,12 @@ bluestein_kernel(FftJob<T> j0, FftJob<T> j1, int p, int M, int logM, int ntubes,
                            ((unsigned)__builtin_bit_cast(unsigned short, lo) << 16);
                 };
                 reinterpret_cast<unsigned*>(dre)[0] = word(yr);
-                reinterpret_cast<unsigned*>(dre)[(size_t)p * dface] = word(yi);
+                reinterpret_cast<unsigned*>(dre)[dplane] = word(yi);
                 continue;
             }
         }
         dre[0] = yr;
-        dre[(size_t)p * dface] = yi;
+        dre[dplane] = yi;
     }
 }
 

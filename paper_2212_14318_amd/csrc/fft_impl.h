@@ -151,6 +151,55 @@ __device__ __forceinline__ unsigned split_bf16_word(float x) {
            ((unsigned)__builtin_bit_cast(unsigned short, lo) << 16);
 }
 
+// Real tubes (the DFT of a real sequence is Hermitian, X^[p - f] =
+// conj(X^[f])): forward from one real plane to faces 0..p/2 of the (Re, Im)
+// planes, inverse from those faces back to the real plane.  sre / dre point
+// at position (i, c) of plane 0; the half-spectrum planes hold H = p/2 + 1
+// faces.
+template <int P, bool INV, typename T, int POL>
+__device__ __forceinline__ void tube_fft_half(const FftJob<T>& jb, const T* __restrict__ sre,
+                                              T* __restrict__ dre, size_t sface, size_t dface,
+                                              const typename Vec2<T>::type* __restrict__ tw) {
+    using V = typename Vec2<T>::type;
+    constexpr int H = P / 2 + 1;
+    V x[P];
+    if constexpr (!INV) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) x[k] = V{sre[k * sface], T(0)};
+    } else {
+        const T* __restrict__ sim = sre + (size_t)H * sface;
+#pragma unroll
+        for (int k = 0; k < H; ++k) x[k] = V{sre[k * sface], sim[k * sface]};
+#pragma unroll
+        for (int k = H; k < P; ++k) x[k] = V{x[P - k].x, -x[P - k].y};
+    }
+    Dft<P, P, INV, V, POL>::run(x, tw);
+    if constexpr (!INV) {
+        T* __restrict__ dim = dre + (size_t)H * dface;
+        if constexpr (sizeof(T) == 4) {
+            if (jb.pack) {
+                unsigned* ure = reinterpret_cast<unsigned*>(dre);
+                unsigned* uim = reinterpret_cast<unsigned*>(dim);
+#pragma unroll
+                for (int k = 0; k < H; ++k) {
+                    ure[k * dface] = split_bf16_word(x[k].x);
+                    uim[k * dface] = split_bf16_word(x[k].y);
+                }
+                return;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            dre[k * dface] = x[k].x;
+            dim[k * dface] = x[k].y;
+        }
+    } else {
+        const T scale = T(1) / T(P);
+#pragma unroll
+        for (int k = 0; k < P; ++k) dre[k * dface] = x[k].x * scale;
+    }
+}
+
 // Transform one complex tube: part 0 = X1 (planes 0, 1), part 1 = X2
 // (planes 2, 3) at flattened position e = i * cols + c of job jb.
 template <int P, bool INV, typename T, int POL = 0>
@@ -166,6 +215,10 @@ __device__ __forceinline__ void tube_fft_one(const FftJob<T>& jb, int part, long
     T* __restrict__ dre = jb.dst + (size_t)(2 * part) * P * dface + (size_t)i * jb.dst_ld + c;
     T* __restrict__ dim = dre + (size_t)P * dface;
 
+    if (jb.half) {
+        tube_fft_half<P, INV, T, POL>(jb, sre, dre, sface, dface, tw);
+        return;
+    }
     V x[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) x[k] = V{sre[k * sface], sim[k * sface]};

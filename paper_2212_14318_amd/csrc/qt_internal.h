@@ -28,6 +28,11 @@ struct FftJob {
     int rows, cols, src_ld, dst_ld;
     int pack;
     int parts = 2;            // CD parts to transform: 2 (quaternion) or 1 (complex, planes 0 and 1)
+    // Hermitian half spectrum (real tensors, parts = 1): forward reads one
+    // real plane of p faces and writes faces 0..p/2 of two planes; inverse
+    // reads those p/2 + 1 faces (the rest are conj(X^[p - f])) and writes
+    // the real plane of p faces.
+    int half = 0;
 };
 
 // Bluestein tables of one p (lengths without a register-resident kernel):

@@ -137,12 +137,43 @@ def tprod_complex(A: torch.Tensor, B: torch.Tensor, precision="fp32", out: torch
         out = torch.empty((2, p, m, s), dtype=A.dtype, device=A.device)
     else:
         _check_tensor(out, "out", nat.QT_FP32, planes=2)
+        if tuple(out.shape) != (2, p, m, s):
+            raise ValueError("out must have shape (2, p, m, s)")
     need = nat.qt_complex_workspace_size(m, n, s, p, prec)
     if ws is None or ws.numel() < need:
         ws = workspace(need, A.device)
     st = nat.qt_tprod_complex(m, n, s, p, A.data_ptr(), B.data_ptr(), out.data_ptr(), prec,
                               ws.data_ptr(), ws.numel(), _stream(A.device))
     nat.check(st, "qt_tprod_complex")
+    return out
+
+
+def tprod_real(A: torch.Tensor, B: torch.Tensor, precision="fp32", out: torch.Tensor | None = None,
+               ws: torch.Tensor | None = None) -> torch.Tensor:
+    """C = A * B for real tensors of shape (p, rows, cols): frequencies
+    0..p/2 only (Hermitian spectrum), one complex product each."""
+    prec = _prec(precision)
+    for x, name in ((A, "A"), (B, "B")):
+        if not isinstance(x, torch.Tensor) or x.dim() != 3:
+            raise ValueError(f"{name} must be a tensor of shape (p, rows, cols)")
+    _check_tensor(A.unsqueeze(0), "A", nat.QT_FP32, planes=1)
+    _check_tensor(B.unsqueeze(0), "B", nat.QT_FP32, planes=1)
+    p, m, n = A.shape
+    if B.shape[0] != p or B.shape[1] != n:
+        raise ValueError("B must be n x s x p with A m x n x p")
+    s = B.shape[2]
+    if out is None:
+        out = torch.empty((p, m, s), dtype=A.dtype, device=A.device)
+    else:
+        _check_tensor(out.unsqueeze(0), "out", nat.QT_FP32, planes=1)
+        if tuple(out.shape) != (p, m, s):
+            raise ValueError("out must have shape (p, m, s)")
+    need = nat.qt_real_workspace_size(m, n, s, p, prec)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, A.device)
+    st = nat.qt_tprod_real(m, n, s, p, A.data_ptr(), B.data_ptr(), out.data_ptr(), prec,
+                           ws.data_ptr(), ws.numel(), _stream(A.device))
+    nat.check(st, "qt_tprod_real")
     return out
 
 

@@ -130,6 +130,29 @@ def test_complex_workspace_formula(m, n, s, p):
     assert nat.qt_complex_workspace_size(m, n, s, p, nat.QT_FP64) == 0
 
 
+@pytest.mark.parametrize("m,n,s,p", [(1, 1, 1, 1), (17, 5, 33, 7), (256, 256, 256, 64), (9, 9, 9, 97)])
+def test_real_workspace_formula(m, n, s, p):
+    h = p // 2 + 1
+    part = lambda r, c: (2 * h * r * ((c + 3) // 4 * 4) * 4 + 255) // 256 * 256
+    want = part(m, n) + part(n, s) + part(m, s)
+    for prec in (nat.QT_FP32, nat.QT_SPLIT_BF16):
+        assert nat.qt_real_workspace_size(m, n, s, p, prec) == want
+    assert nat.qt_real_workspace_size(m, n, s, p, nat.QT_SPLIT_FP16) == 0
+
+
+def test_real_rejects_bad_args():
+    a, b, c = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20), ctypes.c_void_p(3 << 20)
+    w = ctypes.c_void_p(4 << 20)          # never dereferenced: rejected before any launch
+    ws_n = nat.qt_real_workspace_size(4, 4, 4, 4, nat.QT_FP32)
+    assert nat.qt_tprod_real(4, 0, 4, 4, a, b, c, nat.QT_FP32, w, ws_n, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_real(4, 4, 4, 4, a, None, c, nat.QT_FP32, w, ws_n, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_real(4, 4, 4, 4, a, b, c, nat.QT_SPLIT_FP16, w, ws_n, None) == nat.QT_ERR_UNSUPPORTED
+    assert nat.qt_tprod_real(4, 4, 4, 4, a, b, c, nat.QT_FP32, w, ws_n - 1, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_real(4, 4, 4, 4, a, b, b, nat.QT_FP32, w, ws_n, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_real(4, 4, 4, 4, a, b, c, nat.QT_FP32, ctypes.c_void_p((4 << 20) + 4), ws_n,
+                             None) == nat.QT_ERR_INVALID_ARG
+
+
 def test_complex_rejects_bad_args():
     buf = ctypes.c_void_p(1 << 20)       # never dereferenced: rejected before any launch
     ws_n = nat.qt_complex_workspace_size(4, 4, 4, 4, nat.QT_FP32)
