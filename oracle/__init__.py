@@ -23,7 +23,10 @@ quaternion : element and matrix algebra (Hamilton product, conjugates).
 tproduct   : bcirc / unfold / fold, the definitional T-product, its sampled
              entries, the tensor conjugate transpose, identity tensor, the
              least-squares loss and its adjoints, error norms.
+fast       : the paper's FFT-based Algorithm 5.1 in FP64 (the CPU FFT-based
+             version the benchmark times; pinned against the definition).
 """
+from .fast import tprod_fft  # noqa: F401
 from .quaternion import qmul, qmatmul, qconj, qconjT, qnorm2  # noqa: F401
 from .tproduct import (  # noqa: F401
     bcirc,
