@@ -122,16 +122,18 @@ __global__ void __launch_bounds__(256) facewise_f64_valu(FacewiseArgs<double> a)
 // ------------------------------------------------------ complex products
 // A2 = B2 = 0 (complex tensors, the paper's Algorithm 2.1 / Proposition 2.1
 // case): C^[f] = A^[f] B^[f] with no coupling, two A planes and two B planes
-// per chunk, so a 256 x 64 tile fits in 80 KB of LDS; 8 waves (4 x 2), each
-// 64 x 32 (four independent accumulator chains).
-constexpr int kCxMT = 256, kCxNT = 64;
+// per chunk.  8 waves (4 x 2).  256 x 128 (96 KB of LDS, each wave 64 x 64)
+// holds as many products per chunk and barrier as the quaternion tile;
+// 128 x 128 (64 KB, two workgroups per CU) is used when the large tiles
+// would fill the chip fewer than kCxWaves times.
+constexpr int kCxWaves = 3;
 
-template <int MODE>
+template <int MODE, int MT, int NT>
 __global__ void __launch_bounds__(512) facewise_cx_kernel(FacewiseArgs<float> a, TileGrid tg) {
-    __shared__ __attribute__((aligned(16))) V2Smem<kCxMT, kCxNT, true> sm;
+    __shared__ __attribute__((aligned(16))) V2Smem<MT, NT, true> sm;
     int f, tm, tn;
     if (!tile_of_block(tg, f, tm, tn)) return;
-    tile_v2<MODE, kCxMT, kCxNT, 8, false, true>(a, f, tm * kCxMT, tn * kCxNT, 1.f, 1.f, sm);
+    tile_v2<MODE, MT, NT, 8, false, true>(a, f, tm * MT, tn * NT, 1.f, 1.f, sm);
 }
 
 // ---------------------------------------------------- narrow products (s <= 4)
@@ -359,14 +361,29 @@ hipError_t launch_facewise_f32(const FacewiseArgs<float>& a, int precision, hipS
     }
 }
 
-hipError_t launch_facewise_cx(const FacewiseArgs<float>& a, int precision, hipStream_t stream) {
-    const int tiles_m = (a.m + kCxMT - 1) / kCxMT, tiles_n = (a.s + kCxNT - 1) / kCxNT;
+template <int MT, int NT>
+hipError_t launch_cx(const FacewiseArgs<float>& a, int precision, hipStream_t stream) {
+    const int tiles_m = (a.m + MT - 1) / MT, tiles_n = (a.s + NT - 1) / NT;
     const TileGrid tg{tiles_m, tiles_n, a.p};
     const dim3 grid((unsigned)(tiles_m * tiles_n * a.p)), block(512);
-    if (precision == 0) hipLaunchKernelGGL(facewise_cx_kernel<0>, grid, block, 0, stream, a, tg);
-    else if (precision == 1) hipLaunchKernelGGL(facewise_cx_kernel<1>, grid, block, 0, stream, a, tg);
-    else return hipErrorNotSupported;
+    if (precision == 0) hipLaunchKernelGGL((facewise_cx_kernel<0, MT, NT>), grid, block, 0, stream, a, tg);
+    else hipLaunchKernelGGL((facewise_cx_kernel<1, MT, NT>), grid, block, 0, stream, a, tg);
     return hipGetLastError();
+}
+
+static int cx_big_tile(int m, int s, int p, int cus) {
+    const long big = (long)((m + 255) / 256) * ((s + 127) / 128) * p;
+    return big >= (long)kCxWaves * cus ? 1 : 0;
+}
+
+hipError_t launch_facewise_cx(const FacewiseArgs<float>& a, int precision, hipStream_t stream) {
+    if (precision != 0 && precision != 1) return hipErrorNotSupported;
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    return cx_big_tile(a.m, a.s, a.p, cus) ? launch_cx<256, 128>(a, precision, stream)
+                                           : launch_cx<128, 128>(a, precision, stream);
 }
 
 hipError_t launch_facewise_f64(const FacewiseArgs<double>& a, hipStream_t stream) {

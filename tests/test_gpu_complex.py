@@ -13,7 +13,7 @@ import synth
 from paper_2212_14318_amd import _native as nat
 from paper_2212_14318_amd import tprod_complex
 
-from gpu_util import device, rel_err, to_dev, to_np
+from gpu_util import device, rel_err, sample_indices, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -51,6 +51,22 @@ def test_complex_tprod(m, n, s, p, prec):
     ref = oracle.tprod(_as_quat(A), _as_quat(B))
     assert np.abs(ref[2:]).max() == 0.0
     assert rel_err(to_np(C), ref[:2]) < TOLS[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_complex_large_tile_sampled(prec):
+    """2 x 3 x 128 = 768 tiles of 256 x 128: the large complex tile (ragged in
+    m and s), checked on sampled entries computed one by one."""
+    m, n, s, p = 300, 40, 260, 128
+    A = _complex(m, n, p, seed=1900)
+    B = _complex(n, s, p, seed=1901)
+    C = to_np(tprod_complex(to_dev(A), to_dev(B), precision=prec))
+    k, i, j = sample_indices(p, m, s, 6, seed=1902, per_face=True)
+    ref = oracle.tprod_entries(_as_quat(A), _as_quat(B), k, i, j)
+    assert np.abs(ref[2:]).max() == 0.0
+    got = C[:, k, i, j]
+    err = float(np.sqrt(np.sum((got - ref[:2]) ** 2)) / np.sqrt(np.sum(ref[:2] ** 2)))
+    assert err < TOLS[prec]
 
 
 def test_complex_oracle_agrees_with_bcirc_definition():

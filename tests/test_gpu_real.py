@@ -12,7 +12,7 @@ import synth
 from paper_2212_14318_amd import _native as nat
 from paper_2212_14318_amd import tprod_complex, tprod_real
 
-from gpu_util import device, rel_err, to_dev, to_np
+from gpu_util import device, rel_err, sample_indices, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -49,6 +49,22 @@ def test_real_tprod(m, n, s, p, prec):
     ref = oracle.tprod(_as_quat(A), _as_quat(B))
     assert np.abs(ref[1:]).max() == 0.0
     assert rel_err(to_np(C), ref[0]) < TOLS[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_real_large_tile_sampled(prec):
+    """p = 256 keeps 129 frequencies: 2 x 3 x 129 tiles of 256 x 128 (ragged in
+    m and s), checked on sampled entries computed one by one."""
+    m, n, s, p = 300, 20, 260, 256
+    A = _real(m, n, p, seed=3200)
+    B = _real(n, s, p, seed=3201)
+    C = to_np(tprod_real(to_dev(A), to_dev(B), precision=prec))
+    k, i, j = sample_indices(p, m, s, 4, seed=3202, per_face=True)
+    ref = oracle.tprod_entries(_as_quat(A), _as_quat(B), k, i, j)
+    assert np.abs(ref[1:]).max() == 0.0
+    got = C[k, i, j]
+    err = float(np.sqrt(np.sum((got - ref[0]) ** 2)) / np.sqrt(np.sum(ref[0] ** 2)))
+    assert err < TOLS[prec]
 
 
 def test_real_oracle_agrees_with_bcirc_definition():
