@@ -42,6 +42,29 @@ def test_tube_fft_matches_numpy(p):
     assert rel_err(back, X) < 2e-6
 
 
+@pytest.mark.parametrize("rows,cols,p", [(70, 45, 32), (33, 101, 45), (300, 7, 16), (64, 64, 12), (50, 257, 64)])
+def test_tube_fft_unaligned_faces(rows, cols, p):
+    """Faces whose size is not a multiple of 32 reals (each face starts at a
+    different offset within a cache line), multi-block: forward from the
+    dense layout into padded Fourier rows (FP32 and split words), inverse from
+    the padded rows back to the dense layout.  64 x 64 is the aligned control."""
+    X = synth.quat_tensor(rows, cols, p, seed=170 + p)
+    dev = device()
+    F = torch.empty((4, p, rows, nat.qt_fourier_ld(cols)), device=dev)
+    tube_fft(to_dev(X), out=F)
+    w1 = np.fft.fft(X[0] + 1j * X[1], axis=0)
+    w2 = np.fft.fft(X[2] + 1j * X[3], axis=0)
+    want = np.stack([w1.real, w1.imag, w2.real, w2.imag])
+    assert rel_err(to_np(F[..., :cols]), want) < 2e-6
+    back = torch.empty((4, p, rows, cols), device=dev)
+    tube_fft(F, inverse=True, cols=cols, out=back)
+    assert rel_err(to_np(back), X) < 2e-6
+    W = torch.empty_like(F)
+    tube_fft(to_dev(X), precision="split_bf16", out=W)
+    hi, lo = _unpack_split_words(W[..., :cols])
+    assert rel_err(hi + lo, want) < 2e-5
+
+
 def _unpack_split_words(t):
     """(hi | lo << 16) bf16 words -> hi + lo as float64."""
     w = t.contiguous().view(torch.int32).cpu().numpy().astype(np.int64) & 0xFFFFFFFF
