@@ -362,17 +362,38 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     // inter: the DMA of interior chunk c + 1 is issued in slices between the
     // plane steps (mask and inter are literals at every call)
     auto compute = [&](int c, int b, bool mask, bool inter) {
+        // A fragments of the chunk, read and formed once for all NB column blocks
+        float xa[MODE == 0 ? MB : 1][4][8];
+        V8 ah[MB][4], al[MB][4];
+        if constexpr (MODE == 0) {
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) load_a(b, mb, c, mask, xa[mb]);
+        } else {
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                if constexpr (MODE == 1) {
+                    unsigned wa[4][8];
+                    load_a_words(b, mb, c, mask, wa);
+#pragma unroll
+                    for (int pl = 0; pl < NPA; ++pl) unpack8(wa[pl], ah[mb][pl], al[mb][pl]);
+                } else {
+                    float xs[4][8];
+                    load_a(b, mb, c, mask, xs);
+#pragma unroll
+                    for (int pl = 0; pl < NPA; ++pl) split8<H>(xs[pl], ah[mb][pl], al[mb][pl]);
+                }
+            }
+        }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int cl = wn * (NT / 2) + nb * 32 + lr;
             const bool col_ok = !mask || (n0 + cl < a.s);
+            // the DMA slices of chunk c + 1 go out once, with the first column block
+            const bool dma = inter && nb == 0;
             if constexpr (MODE == 0) {
-                float xa[MB][4][8];
-#pragma unroll
-                for (int mb = 0; mb < MB; ++mb) load_a(b, mb, c, mask, xa[mb]);
 #pragma unroll
                 for (int q = 0; q < NPB; ++q) {
-                    if (inter) {
+                    if (dma) {
 #pragma unroll
                         for (int sl = q * 8 / NPB; sl < (q + 1) * 8 / NPB; ++sl) issue_slice(c + 1, sl);
                     }
@@ -403,21 +424,6 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                         }
                 }
             } else {
-                V8 ah[MB][4], al[MB][4];
-#pragma unroll
-                for (int mb = 0; mb < MB; ++mb) {
-                    if constexpr (MODE == 1) {
-                        unsigned wa[4][8];
-                        load_a_words(b, mb, c, mask, wa);
-#pragma unroll
-                        for (int pl = 0; pl < NPA; ++pl) unpack8(wa[pl], ah[mb][pl], al[mb][pl]);
-                    } else {
-                        float xa[4][8];
-                        load_a(b, mb, c, mask, xa);
-#pragma unroll
-                        for (int pl = 0; pl < NPA; ++pl) split8<H>(xa[pl], ah[mb][pl], al[mb][pl]);
-                    }
-                }
                 // all B words of the chunk are read up front, so that their LDS
                 // latency overlaps the products of the earlier planes
                 unsigned wb[8][8];
@@ -458,7 +464,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                     // complex: plane 0 (Re B) and plane 1 (Im B) of C1 alone
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
-                        if (inter) {
+                        if (dma) {
 #pragma unroll
                             for (int sl = 4 * q; sl < 4 * q + 4; ++sl) issue_slice(c + 1, sl);
                         }
@@ -492,7 +498,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
 #pragma unroll
                 for (int qp = 0; qp < 4; ++qp) {
                     const int qa = (qp & 1) | ((qp & 2) << 1), qb = qa + 2;
-                    if (inter) {
+                    if (dma) {
                         issue_slice(c + 1, 2 * qp);
                         issue_slice(c + 1, 2 * qp + 1);
                     }
