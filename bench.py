@@ -52,6 +52,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    """Host CPU model name (Linux), or the platform string."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def flops(m, n, s, p):
     f_gemm = 32.0 * m * n * s * p
     f_fft = 10.0 * p * math.log2(p) * (m * n + n * s + m * s) if p > 1 else 0.0
@@ -269,23 +282,27 @@ def main():
         t_cpu = time.perf_counter() - t0
         frac = faces_done / p
         cpu = {"value": F * frac / t_cpu / 1e12, "unit": "TFLOP/s-equiv", "cores": int(threads),
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"{faces_done} of {p} output faces of the same workload (FP64 "
                          f"definition, block-row form), {t_cpu:.1f} s; value = F x {faces_done}/{p} / time"}
         log(f"[bench] oracle CPU baseline: {cpu['value']:.4g} TFLOP/s-equiv on {threads} threads "
             f"({faces_done} faces in {t_cpu:.1f}s)")
-        # the paper's FFT-based Algorithm 5.1 on the host (FP64 numpy), whole workload
-        t0 = time.perf_counter()
-        Cf = oracle.tprod_fft(A64, B64)
-        t_fft = time.perf_counter() - t0
-        err_fft = float(np.sqrt(np.sum((Cf[:, kk, ii, jj] - ref) ** 2)) / np.sqrt(np.sum(ref ** 2)))
-        del Cf
-        cpu_fft = {"value": F / t_fft / 1e12, "unit": "TFLOP/s-equiv", "cores": int(threads),
-                   "kind": "oracle_fft",
-                   "sample": f"whole workload by Algorithm 5.1 (numpy FFT + complex128 products), "
-                             f"{t_fft:.1f} s, sampled rel. error vs the definition {err_fft:.1e}"}
-        log(f"[bench] CPU FFT-based (Algorithm 5.1, FP64): {cpu_fft['value']:.4g} TFLOP/s-equiv on "
-            f"{threads} threads ({t_fft:.1f}s)")
+        # the paper's FFT-based Algorithm 5.1 on the host, whole workload, in FP64
+        # (complex128) and FP32 (complex64)
+        cpu_fft = {}
+        for label, cdt in (("fp64", np.complex128), ("fp32", np.complex64)):
+            t0 = time.perf_counter()
+            Cf = oracle.tprod_fft(A64, B64, dtype=cdt)
+            t_fft = time.perf_counter() - t0
+            err_fft = float(np.sqrt(np.sum((Cf[:, kk, ii, jj] - ref) ** 2)) / np.sqrt(np.sum(ref ** 2)))
+            del Cf
+            cpu_fft[label] = {"value": F / t_fft / 1e12, "unit": "TFLOP/s-equiv", "cores": int(threads),
+                              "kind": "oracle_fft", "cpu_model": cpu_model(),
+                              "sample": f"whole workload by Algorithm 5.1 (numpy FFT + {np.dtype(cdt).name} "
+                                        f"products), {t_fft:.1f} s, sampled rel. error vs the definition "
+                                        f"{err_fft:.1e}"}
+            log(f"[bench] CPU FFT-based (Algorithm 5.1, {label}): {cpu_fft[label]['value']:.4g} "
+                f"TFLOP/s-equiv on {threads} threads ({t_fft:.1f}s, rel err {err_fft:.1e})")
 
     head = precs[0] if precs[0] in results else next(iter(results))
     r = results[head]

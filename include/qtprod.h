@@ -47,6 +47,16 @@
  * Preconditions checked (QT_ERR_INVALID_ARG otherwise): m, n, s, p >= 1;
  * every pointer non-NULL and 16-byte aligned; outputs do not overlap inputs;
  * ws_bytes >= the matching *_workspace_size(); 4 * p * rows * cols < 2^40.
+ *
+ * Workspace.  The one-shot products (qt_tprod, qt_tprod_complex,
+ * qt_tprod_real, qt_tprod_backward, qt_tprod_batched) also accept ws == NULL
+ * with ws_bytes == 0: the call then takes its workspace from the
+ * stream-ordered allocator (hipMallocAsync on `stream`) and returns it
+ * (hipFreeAsync on `stream`) after its kernels, with no host synchronisation;
+ * an allocation failure returns QT_ERR_ALLOC.  Callers that capture graphs or
+ * must not allocate pass their own buffer.  ws == NULL with ws_bytes != 0 is
+ * QT_ERR_INVALID_ARG.  Plans (qt_batched_plan_create) always need a caller
+ * buffer.
  */
 #ifndef QTPROD_H
 #define QTPROD_H
@@ -62,7 +72,7 @@ typedef enum {
     QT_OK = 0,
     QT_ERR_INVALID_ARG = -1,  /* bad size, pointer, alignment, aliasing, workspace */
     QT_ERR_UNSUPPORTED = -2,  /* valid request this build cannot serve (e.g. p too large) */
-    QT_ERR_ALLOC = -3,        /* plan-cache allocation failed */
+    QT_ERR_ALLOC = -3,        /* device allocation failed (plan cache, or a workspace requested with ws == NULL) */
     QT_ERR_HIP = -4           /* a HIP runtime call or kernel launch failed */
 } qt_status;
 

@@ -32,22 +32,25 @@ def _parts(X: np.ndarray):
     return X[0] + 1j * X[1], X[2] + 1j * X[3]
 
 
-def tprod_fft(A: np.ndarray, B: np.ndarray) -> np.ndarray:
-    """C = A * B by Algorithm 5.1; A (4, p, m, n), B (4, p, n, s) float64."""
+def tprod_fft(A: np.ndarray, B: np.ndarray, dtype=np.complex128) -> np.ndarray:
+    """C = A * B by Algorithm 5.1; A (4, p, m, n), B (4, p, n, s).
+
+    dtype: complex type of the Fourier-domain work (complex128, the oracle
+    precision; complex64 gives the single-precision CPU baseline)."""
     if A.ndim != 4 or B.ndim != 4 or A.shape[0] != 4 or B.shape[0] != 4:
         raise ValueError("quaternion tensors must have shape (4, p, rows, cols)")
     if A.shape[1] != B.shape[1] or A.shape[3] != B.shape[2]:
         raise ValueError("A must be m x n x p and B n x s x p")
     p = A.shape[1]
-    A1, A2 = _parts(A)
-    B1, B2 = _parts(B)
+    A1, A2 = (x.astype(dtype) for x in _parts(A))
+    B1, B2 = (x.astype(dtype) for x in _parts(B))
     # Step 1
     hA1, hA2 = np.fft.fft(np.conj(A1), axis=0), -np.fft.fft(A2, axis=0)
     hB1, hB2 = np.fft.fft(np.conj(B1), axis=0), -np.fft.fft(B2, axis=0)
     # Step 2 (0-based face f = i - 1; r - 1 = (p + 1 - i) mod p = (-f) mod p)
     m, s = A.shape[2], B.shape[3]
-    hC1 = np.empty((p, m, s), complex)
-    hC2 = np.empty((p, m, s), complex)
+    hC1 = np.empty((p, m, s), dtype)
+    hC2 = np.empty((p, m, s), dtype)
     for f in range(p):
         r = (-f) % p
         hC1[f] = hA1[r] @ hB1[r] - np.conj(hA2[f]) @ hB2[r]

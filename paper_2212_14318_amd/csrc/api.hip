@@ -7,6 +7,7 @@
 #include <unordered_map>
 
 #include "qt_internal.h"
+#include "workspace.h"
 #include "../../include/qtprod.h"
 
 namespace {
@@ -266,7 +267,7 @@ const char* qt_status_string(int status) {
         case QT_OK: return "QT_OK";
         case QT_ERR_INVALID_ARG: return "QT_ERR_INVALID_ARG: invalid size, pointer, alignment, aliasing or workspace";
         case QT_ERR_UNSUPPORTED: return "QT_ERR_UNSUPPORTED: request not supported by this build";
-        case QT_ERR_ALLOC: return "QT_ERR_ALLOC: plan allocation failed";
+        case QT_ERR_ALLOC: return "QT_ERR_ALLOC: device allocation failed";
         case QT_ERR_HIP: return "QT_ERR_HIP: HIP runtime or launch error";
         default: return "unknown qt_status";
     }
@@ -352,7 +353,8 @@ size_t qt_workspace_size(int m, int n, int s, int p, int precision) {
     return total;
 }
 
-int qt_tprod(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision,
+namespace {
+int tprod_ws(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision,
              void* ws, size_t ws_bytes, hipStream_t stream) {
     if (!valid_precision(precision)) return QT_ERR_INVALID_ARG;
     if (!dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p)) return QT_ERR_INVALID_ARG;
@@ -372,6 +374,13 @@ int qt_tprod(int m, int n, int s, int p, const void* A, const void* B, void* C, 
                                  (char*)ws, stream);
     return run_tprod<float>(m, n, s, p, (const float*)A, (const float*)B, (float*)C, precision,
                             (char*)ws, stream);
+}
+}  // namespace
+
+int qt_tprod(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision,
+             void* ws, size_t ws_bytes, hipStream_t stream) {
+    return qt::with_workspace(ws, ws_bytes, qt_workspace_size(m, n, s, p, precision), stream,
+                              [&](void* w, size_t wb) { return tprod_ws(m, n, s, p, A, B, C, precision, w, wb, stream); });
 }
 
 // ------------------------------------------- complex and real T-products
@@ -445,7 +454,8 @@ size_t qt_complex_workspace_size(int m, int n, int s, int p, int precision) {
 
 int qt_tprod_complex(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision,
                      void* ws, size_t ws_bytes, hipStream_t stream) {
-    return run_cx(m, n, s, p, A, B, C, precision, ws, ws_bytes, false, stream);
+    return qt::with_workspace(ws, ws_bytes, cx_workspace(m, n, s, p, precision, false), stream,
+                              [&](void* w, size_t wb) { return run_cx(m, n, s, p, A, B, C, precision, w, wb, false, stream); });
 }
 
 size_t qt_real_workspace_size(int m, int n, int s, int p, int precision) {
@@ -454,7 +464,8 @@ size_t qt_real_workspace_size(int m, int n, int s, int p, int precision) {
 
 int qt_tprod_real(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision,
                   void* ws, size_t ws_bytes, hipStream_t stream) {
-    return run_cx(m, n, s, p, A, B, C, precision, ws, ws_bytes, true, stream);
+    return qt::with_workspace(ws, ws_bytes, cx_workspace(m, n, s, p, precision, true), stream,
+                              [&](void* w, size_t wb) { return run_cx(m, n, s, p, A, B, C, precision, w, wb, true, stream); });
 }
 
 size_t qt_backward_workspace_size(int m, int n, int s, int p, int precision) {
@@ -463,9 +474,9 @@ size_t qt_backward_workspace_size(int m, int n, int s, int p, int precision) {
     return backward_layout(m, n, s, p, precision).total;
 }
 
-int qt_tprod_backward(int m, int n, int s, int p, const void* A, const void* B, const void* G,
-                      void* dA, void* dB, int precision, void* ws, size_t ws_bytes,
-                      hipStream_t stream) {
+namespace {
+int backward_ws(int m, int n, int s, int p, const void* A, const void* B, const void* G,
+                void* dA, void* dB, int precision, void* ws, size_t ws_bytes, hipStream_t stream) {
     if (!valid_precision(precision)) return QT_ERR_INVALID_ARG;
     if (!dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p)) return QT_ERR_INVALID_ARG;
     if (!A || !B || !G || !ws) return QT_ERR_INVALID_ARG;
@@ -490,6 +501,16 @@ int qt_tprod_backward(int m, int n, int s, int p, const void* A, const void* B, 
                                     (double*)dA, (double*)dB, precision, (char*)ws, stream);
     return run_backward<float>(m, n, s, p, (const float*)A, (const float*)B, (const float*)G,
                                (float*)dA, (float*)dB, precision, (char*)ws, stream);
+}
+}  // namespace
+
+int qt_tprod_backward(int m, int n, int s, int p, const void* A, const void* B, const void* G,
+                      void* dA, void* dB, int precision, void* ws, size_t ws_bytes,
+                      hipStream_t stream) {
+    return qt::with_workspace(ws, ws_bytes, qt_backward_workspace_size(m, n, s, p, precision), stream,
+                              [&](void* w, size_t wb) {
+                                  return backward_ws(m, n, s, p, A, B, G, dA, dB, precision, w, wb, stream);
+                              });
 }
 
 }  // extern "C"

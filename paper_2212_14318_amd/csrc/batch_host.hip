@@ -12,6 +12,7 @@
 
 #include "batched.h"
 #include "facewise_impl.h"
+#include "workspace.h"
 #include "../../include/qtprod.h"
 
 namespace qt {
@@ -491,6 +492,23 @@ int choose_tile(int m, int n, int s, int precision) {
     return pick_tile(tuned(precision, &t) ? &t : nullptr, m, n, s);
 }
 
+// One-shot batched product on a workspace of ws_bytes (validated here).
+int run_batched(int count, const qt_problem* probs, int precision, void* ws, size_t ws_bytes,
+                hipStream_t stream) {
+    DescLayout L;
+    int st = validate(count, probs, precision, ws, ws_bytes, &L);
+    if (st != QT_OK) return st;
+    TuneTable t;
+    st = ensure_tuned(precision, stream, &t);
+    if (st != QT_OK) return st;
+    HostLists H;
+    st = build_lists(count, probs, precision, (char*)ws, L, t, stream, &H);
+    if (st != QT_OK) return st;
+    st = upload(H, (char*)ws, L, stream);
+    if (st != QT_OK) return st;
+    return enqueue(H, (char*)ws, L, precision, stream);
+}
+
 }  // namespace qt
 
 struct qt_batched_plan_s {
@@ -522,18 +540,8 @@ size_t qt_batched_workspace_size(int count, const qt_problem* probs, int precisi
 
 int qt_tprod_batched(int count, const qt_problem* probs, int precision, void* ws, size_t ws_bytes,
                      hipStream_t stream) {
-    qt::DescLayout L;
-    int st = qt::validate(count, probs, precision, ws, ws_bytes, &L);
-    if (st != QT_OK) return st;
-    qt::TuneTable t;
-    st = qt::ensure_tuned(precision, stream, &t);
-    if (st != QT_OK) return st;
-    qt::HostLists H;
-    st = qt::build_lists(count, probs, precision, (char*)ws, L, t, stream, &H);
-    if (st != QT_OK) return st;
-    st = qt::upload(H, (char*)ws, L, stream);
-    if (st != QT_OK) return st;
-    return qt::enqueue(H, (char*)ws, L, precision, stream);
+    return qt::with_workspace(ws, ws_bytes, qt_batched_workspace_size(count, probs, precision), stream,
+                              [&](void* w, size_t wb) { return qt::run_batched(count, probs, precision, w, wb, stream); });
 }
 
 int qt_batched_plan_create(int count, const qt_problem* probs, int precision, void* ws, size_t ws_bytes,

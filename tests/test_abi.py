@@ -166,6 +166,24 @@ def test_complex_rejects_bad_args():
     assert nat.qt_tprod_complex(4, 4, 4, 4, a, b, a, nat.QT_FP32, w, ws_n, None) == nat.QT_ERR_INVALID_ARG
 
 
+def test_null_workspace_needs_zero_bytes():
+    """ws == NULL asks the library to allocate, which requires ws_bytes == 0
+    and a valid problem; both cases are rejected before any HIP call."""
+    a, b, c = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20), ctypes.c_void_p(3 << 20)
+    g, da, db = ctypes.c_void_p(4 << 20), ctypes.c_void_p(5 << 20), ctypes.c_void_p(6 << 20)
+    inv = nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod(4, 4, 4, 4, a, b, c, nat.QT_FP32, None, 64, None) == inv
+    assert nat.qt_tprod(0, 4, 4, 4, a, b, c, nat.QT_FP32, None, 0, None) == inv
+    assert nat.qt_tprod_complex(4, 4, 4, 4, a, b, c, nat.QT_FP32, None, 64, None) == inv
+    assert nat.qt_tprod_real(4, 4, 0, 4, a, b, c, nat.QT_FP32, None, 0, None) == inv
+    assert nat.qt_tprod_backward(4, 4, 4, 4, a, b, g, da, db, nat.QT_FP32, None, 64, None) == inv
+    assert nat.qt_tprod_backward(4, 4, 4, 0, a, b, g, da, db, nat.QT_FP32, None, 0, None) == inv
+    probs = (nat.qt_problem * 1)(nat.qt_problem(4, 4, 4, 4, a, b, c))
+    assert nat.qt_tprod_batched(1, probs, nat.QT_FP32, None, 64, None) == inv
+    bad = (nat.qt_problem * 1)(nat.qt_problem(0, 4, 4, 4, a, b, c))
+    assert nat.qt_tprod_batched(1, bad, nat.QT_FP32, None, 0, None) == inv
+
+
 def test_split_words_rejects_bad_args():
     buf = ctypes.c_void_p(4096)          # never dereferenced: rejected before any launch
     assert nat.qt_split_words(0, 4, 4, buf, 4, None) == nat.QT_ERR_INVALID_ARG
