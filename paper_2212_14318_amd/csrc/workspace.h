@@ -11,10 +11,17 @@
 
 namespace qt {
 
+// need == 0 (the size query rejected the arguments): run() is called without
+// a workspace, so that its own checks return the precise status
+// (QT_ERR_UNSUPPORTED or QT_ERR_INVALID_ARG); every run() rejects ws == NULL.
 template <typename Run>
 int with_workspace(void* ws, size_t ws_bytes, size_t need, hipStream_t stream, Run&& run) {
     if (ws) return run(ws, ws_bytes);
-    if (ws_bytes != 0 || need == 0) return QT_ERR_INVALID_ARG;
+    if (ws_bytes != 0) return QT_ERR_INVALID_ARG;
+    if (need == 0) {
+        const int st = run(nullptr, 0);
+        return st == QT_OK ? QT_ERR_INVALID_ARG : st;
+    }
     void* tmp = nullptr;
     if (hipMallocAsync(&tmp, need, stream) != hipSuccess) {
         (void)hipGetLastError();

@@ -182,6 +182,10 @@ def test_null_workspace_needs_zero_bytes():
     assert nat.qt_tprod_batched(1, probs, nat.QT_FP32, None, 64, None) == inv
     bad = (nat.qt_problem * 1)(nat.qt_problem(0, 4, 4, 4, a, b, c))
     assert nat.qt_tprod_batched(1, bad, nat.QT_FP32, None, 0, None) == inv
+    # an unsupported precision keeps its own status when the library would allocate
+    uns = nat.QT_ERR_UNSUPPORTED
+    assert nat.qt_tprod_complex(4, 4, 4, 4, a, b, c, nat.QT_FP64, None, 0, None) == uns
+    assert nat.qt_tprod_real(4, 4, 4, 4, a, b, c, nat.QT_SPLIT_FP16, None, 0, None) == uns
 
 
 def test_split_words_rejects_bad_args():
