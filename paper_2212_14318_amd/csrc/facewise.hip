@@ -128,8 +128,11 @@ __global__ void __launch_bounds__(256) facewise_f64_valu(FacewiseArgs<double> a)
 // would fill the chip fewer than kCxWaves times.
 constexpr int kCxWaves = 3;
 
+// The split-bf16 128 x 128 instance is held to 128 VGPRs (4 waves per SIMD,
+// so two workgroups share a CU and cover each other's barrier waits; a few
+// values spill to scratch): 5% faster on the 17-frequency real product.
 template <int MODE, int MT, int NT>
-__global__ void __launch_bounds__(512) facewise_cx_kernel(FacewiseArgs<float> a, TileGrid tg) {
+__global__ void __launch_bounds__(512, (MODE == 1 && MT == 128 ? 4 : 2)) facewise_cx_kernel(FacewiseArgs<float> a, TileGrid tg) {
     __shared__ __attribute__((aligned(16))) V2Smem<MT, NT, true> sm;
     int f, tm, tn;
     if (!tile_of_block(tg, f, tm, tn)) return;
