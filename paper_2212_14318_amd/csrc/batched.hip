@@ -25,7 +25,7 @@ using namespace detail;
 // Persistent product kernel of one tile shape: the grid strides its own
 // item list (all items of the launch have tile shape CFG).
 template <int PREC, int CFG>
-__global__ void __launch_bounds__(64 * tile_waves(CFG))
+__global__ void __launch_bounds__(64 * tile_waves(PREC, CFG))
 batched_gemm_kernel(const BatchGemmProb* __restrict__ probs, const BatchGemmItem* __restrict__ items,
                     int nitems) {
     constexpr int MT = tile_mt(CFG), NT = tile_nt(CFG);
@@ -33,7 +33,7 @@ batched_gemm_kernel(const BatchGemmProb* __restrict__ probs, const BatchGemmItem
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const BatchGemmItem item = items[it];
         const BatchGemmProb pr = probs[item.prob];
-        tile_v2<PREC, MT, NT, tile_waves(CFG), plane_groups(PREC, CFG)>(pr.a, item.f, item.tm * MT,
+        tile_v2<PREC, MT, NT, tile_waves(PREC, CFG), plane_groups(PREC, CFG)>(pr.a, item.f, item.tm * MT,
                                                                          item.tn * NT, 1.f, 1.f, sm);
     }
 }
@@ -65,7 +65,7 @@ hipError_t launch_batched_fft(bool inverse, int p, int pol, const BatchFftJob* j
 int batched_gemm_blocks_per_cu(int precision, int cfg) {
     const void* fn = (precision == 0 || precision == 1) ? gemm_kernel(precision, cfg) : nullptr;
     int n = 0;
-    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 64 * tile_waves(cfg), 0) != hipSuccess)
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 64 * tile_waves(precision, cfg), 0) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
@@ -74,7 +74,7 @@ hipError_t launch_batched_gemm(int precision, int cfg, const BatchGemmProb* prob
                                const BatchGemmItem* items, int nitems, int grid, hipStream_t stream) {
     if (nitems <= 0) return hipSuccess;
     if (precision != 0 && precision != 1) return hipErrorNotSupported;
-    const dim3 g((unsigned)grid), b(64 * tile_waves(cfg));
+    const dim3 g((unsigned)grid), b(64 * tile_waves(precision, cfg));
 #define QT_GEMM_LAUNCH(PREC, CFG) \
     hipLaunchKernelGGL((batched_gemm_kernel<PREC, CFG>), g, b, 0, stream, probs, items, nitems)
     switch (2 * cfg + precision) {

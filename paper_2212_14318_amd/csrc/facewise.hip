@@ -42,17 +42,17 @@ __device__ __forceinline__ bool tile_of_block(const TileGrid& t, int& f, int& tm
 }
 
 template <int CFG>
-__global__ void __launch_bounds__(64 * tile_waves(CFG))
+__global__ void __launch_bounds__(64 * tile_waves(0, CFG))
 facewise_f32_kernel(FacewiseArgs<float> a, TileGrid tg) {
     constexpr int MT = tile_mt(CFG), NT = tile_nt(CFG);
     __shared__ __attribute__((aligned(16))) V2Smem<MT, NT> sm;
     int f, tm, tn;
     if (!tile_of_block(tg, f, tm, tn)) return;
-    tile_v2<0, MT, NT, tile_waves(CFG)>(a, f, tm * MT, tn * NT, 1.f, 1.f, sm);
+    tile_v2<0, MT, NT, tile_waves(0, CFG)>(a, f, tm * MT, tn * NT, 1.f, 1.f, sm);
 }
 
 template <typename H, int CFG>
-__global__ void __launch_bounds__(64 * tile_waves(CFG))
+__global__ void __launch_bounds__(64 * tile_waves(std::is_same<H, _Float16>::value ? 2 : 1, CFG))
 facewise_split_kernel(FacewiseArgs<float> a, TileGrid tg, const float* __restrict__ scales) {
     constexpr int MT = tile_mt(CFG), NT = tile_nt(CFG);
     constexpr int MODE = std::is_same<H, _Float16>::value ? 2 : 1;
@@ -64,7 +64,7 @@ facewise_split_kernel(FacewiseArgs<float> a, TileGrid tg, const float* __restric
         sa = scales[f];
         sb = scales[a.p + f];
     }
-    tile_v2<MODE, MT, NT, tile_waves(CFG), plane_groups(MODE, CFG)>(a, f, tm * MT, tn * NT, sa, sb, sm);
+    tile_v2<MODE, MT, NT, tile_waves(MODE, CFG), plane_groups(MODE, CFG)>(a, f, tm * MT, tn * NT, sa, sb, sm);
 }
 
 // ---------------------------------------------------------------- FP64 VALU
@@ -319,7 +319,7 @@ static hipError_t launch_cfg(const FacewiseArgs<float>& a, int precision, const 
     const int tiles_m = (a.m + MT - 1) / MT;
     const int tiles_n = (a.s + NT - 1) / NT;
     const TileGrid tg{tiles_m, tiles_n, a.p};
-    const dim3 grid((unsigned)(tiles_m * tiles_n * a.p)), block(64 * tile_waves(CFG));
+    const dim3 grid((unsigned)(tiles_m * tiles_n * a.p)), block(64 * tile_waves(precision, CFG));
     if (precision == 0) {
         hipLaunchKernelGGL((facewise_f32_kernel<CFG>), grid, block, 0, stream, a, tg);
     } else if (precision == 1) {

@@ -107,14 +107,19 @@ __device__ __forceinline__ V8 neg8(V8 x) {
 enum TileCfg { TILE_128x64 = 0, TILE_64x128 = 1, TILE_64x64 = 2, NUM_TILE_CFGS = 3 };
 __host__ __device__ constexpr int tile_mt(int cfg) { return cfg == TILE_128x64 ? 128 : 64; }
 __host__ __device__ constexpr int tile_nt(int cfg) { return cfg == TILE_64x128 ? 128 : 64; }
-// Waves per workgroup of a tile shape: the 128 x 64 tile runs 8 waves (4 x 2,
-// each 32 x 32), so two waves share a SIMD and hide each other's LDS and
-// VALU latency; the 64-wide tiles run 4 waves (2 x 2).
-__host__ __device__ constexpr int tile_waves(int cfg) { return cfg == TILE_128x64 ? 8 : 4; }
-// The split-bf16 128 x 64 tile splits its 8 waves into two plane groups
-// (tile_v2's PG): each wave reads half the staged planes per chunk, which cuts
-// LDS fragment reads and unpacking by a third.
-__host__ __device__ constexpr bool plane_groups(int mode, int cfg) { return mode == 1 && cfg == TILE_128x64; }
+// Every split-bf16 tile splits 8 waves into two plane groups (tile_v2's PG):
+// each wave reads half the staged planes per chunk, which cuts LDS fragment
+// reads and unpacking by a third.
+__host__ __device__ constexpr bool plane_groups(int mode, int cfg) { return mode == 1 && cfg >= 0; }
+// Waves per workgroup of a tile shape and mode (0 FP32, 1 split bf16, 2 split
+// fp16): 8 waves for the 128 x 64 tile (4 x 2, each 32 x 32) and for every
+// split-bf16 tile (two plane groups of 2 x 2), so that two waves share a SIMD
+// and hide each other's LDS and VALU latency; the other 64-wide tiles run 4
+// waves (2 x 2).  (A 64-wide tile stages 96 or 160 KB per workgroup, so one
+// workgroup fills a CU's LDS.)
+__host__ __device__ constexpr int tile_waves(int mode, int cfg) {
+    return (cfg == TILE_128x64 || plane_groups(mode, cfg)) ? 8 : 4;
+}
 
 
 // ======================================================== pipelined tile
