@@ -300,9 +300,17 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     const int wm = tw % WM, wn = tw / WM;
     const int lr = lane & 31, lg = lane >> 5;
 
-    v16f acc[4][MB][NB];
+    // FP32 tiles form each complex product with three real products (KARA):
+    // P1 = Re A Re Y, P2 = Im A Im Y, P3 = (Re A + Im A)(Re Y + Im Y),
+    // accumulated per output (C1, C2; C alone for CX) over its coupled terms,
+    // and Re C = P1 - P2, Im C = P3 - P1 - P2 at the end: 12 real products per
+    // quaternion output pair and k instead of 16 (3 instead of 4 for CX).
+    constexpr bool KARA = MODE == 0;
+    constexpr int NOUT = CX ? 1 : 2;                  // complex outputs per tile
+    constexpr int NACC = KARA ? 3 * NOUT : 4;
+    v16f acc[NACC][MB][NB];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < NACC; ++c)
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -396,36 +404,45 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
             // the DMA slices of chunk c + 1 go out once, with the first column block
             const bool dma = inter && nb == 0;
             if constexpr (MODE == 0) {
+                // A sums Re + Im of A1 and A2 (exact inputs, one FP32 rounding)
+                float xs[MB][NPA / 2][8];
 #pragma unroll
-                for (int q = 0; q < NPB; ++q) {
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int h = 0; h < NPA / 2; ++h)
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) xs[mb][h][t] = xa[mb][2 * h][t] + xa[mb][2 * h + 1][t];
+                // staged B planes in (real, imaginary) pairs: (B1r, B1i) and (B2r, B2i)
+                // with A1, (Dr, Di) and (Er, Ei) with A2; the first and third
+                // feed C1, the second and fourth C2 (CX: the one pair (Br, Bi))
+                constexpr int NPP = NPB / 2;
+#pragma unroll
+                for (int pp = 0; pp < NPP; ++pp) {
                     if (dma) {
 #pragma unroll
-                        for (int sl = q * 8 / NPB; sl < (q + 1) * 8 / NPB; ++sl) issue_slice(c + 1, sl);
+                        for (int sl = pp * 8 / NPP; sl < (pp + 1) * 8 / NPP; ++sl) issue_slice(c + 1, sl);
                     }
-                    const float sgn = (q == 4 || q == 7) ? -1.f : 1.f;
-                    float y[8], ny[8];
+                    float yr[8], yi[8], ys[8];
 #pragma unroll
                     for (int j = 0; j < 8; ++j) {
                         const int k = 8 * lg + j;
-                        const float v = sm.B[b][q][k / RB][(k % RB) * NT + cl];
                         const bool ok = col_ok && (!mask || (c * KT + k < a.n));
-                        y[j] = ok ? v * sgn : 0.f;
-                        ny[j] = -y[j];
+                        const float vr = sm.B[b][2 * pp][k / RB][(k % RB) * NT + cl];
+                        const float vi = sm.B[b][2 * pp + 1][k / RB][(k % RB) * NT + cl];
+                        // D = (-B2r, B2i), E = (B1r, -B1i) at -f
+                        yr[j] = ok ? (pp == 2 ? -vr : vr) : 0.f;
+                        yi[j] = ok ? (pp == 3 ? -vi : vi) : 0.f;
+                        ys[j] = yr[j] + yi[j];
                     }
-                    const int cre = (q & 2) ? 2 : 0;          // ReC1 / ReC2
-                    const int apl = (q & 4) ? 2 : 0;          // A1 / A2 real plane
+                    const int ca = (pp & 1) ? 3 : 0;          // P1, P2, P3 of C1 or C2
+                    const int apl = (pp & 2) ? 2 : 0;         // A1 or A2
 #pragma unroll
                     for (int t = 0; t < 8; ++t)
 #pragma unroll
                         for (int mb = 0; mb < MB; ++mb) {
-                            const float ar = xa[mb][apl][t], ai = xa[mb][apl + 1][t];
-                            if ((q & 1) == 0) {   // real B part: Re += Ar Y, Im += Ai Y
-                                acc[cre][mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, y[t], acc[cre][mb][nb], 0, 0, 0);
-                                acc[cre + 1][mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, y[t], acc[cre + 1][mb][nb], 0, 0, 0);
-                            } else {              // imaginary B part: Re -= Ai Y, Im += Ar Y
-                                acc[cre][mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, ny[t], acc[cre][mb][nb], 0, 0, 0);
-                                acc[cre + 1][mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, y[t], acc[cre + 1][mb][nb], 0, 0, 0);
-                            }
+                            acc[ca][mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[mb][apl][t], yr[t], acc[ca][mb][nb], 0, 0, 0);
+                            acc[ca + 1][mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[mb][apl + 1][t], yi[t], acc[ca + 1][mb][nb], 0, 0, 0);
+                            acc[ca + 2][mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[mb][apl / 2][t], ys[t], acc[ca + 2][mb][nb], 0, 0, 0);
                         }
                 }
             } else {
@@ -713,6 +730,21 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                         for (int r = 0; r < 16; ++r) acc[keep + c2][mb][nb][r] += theirs[(size_t)(idx++) * LANES + slot];
             __syncthreads();                 // LDS may be reused by the next tile
             store_tile<MB, NB, keep, 2>(a, f, row0, col0, acc, scale, lane);
+        } else if constexpr (KARA) {
+            v16f out[4][MB][NB];
+#pragma unroll
+            for (int h = 0; h < NOUT; ++h)
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const float p1 = acc[3 * h][mb][nb][r], p2 = acc[3 * h + 1][mb][nb][r];
+                            out[2 * h][mb][nb][r] = p1 - p2;
+                            out[2 * h + 1][mb][nb][r] = acc[3 * h + 2][mb][nb][r] - p1 - p2;
+                        }
+            store_tile<MB, NB, 0, 2 * NOUT>(a, f, row0, col0, out, scale, lane);
         } else {
             store_tile<MB, NB, 0, CX ? 2 : 4>(a, f, row0, col0, acc, scale, lane);
         }
