@@ -300,16 +300,12 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     const int wm = tw % WM, wn = tw / WM;
     const int lr = lane & 31, lg = lane >> 5;
 
-    // FP32 and split-fp16 tiles form each complex product with three real
-    // products (KARA): P1 = Re A Re Y, P2 = Im A Im Y, P3 = (Re A + Im A)(Re Y
-    // + Im Y), accumulated per output (C1, C2; C alone for CX) over its coupled
-    // terms, and Re C = P1 - P2, Im C = P3 - P1 - P2 at the end: 12 real
-    // products per quaternion output pair and k instead of 16 (3 instead of 4
-    // for CX).  (Split fp16 forms its fragments from FP32 values, so a sum
-    // costs one FP32 addition before the split; the split-bf16 operands are
-    // pre-split words.)
-    constexpr bool KARA = MODE == 0 || (MODE == 2 && !CX);
-    constexpr float P3F = MODE == 2 ? 4.f : 1.f;      // split fp16 accumulates P3 / 4
+    // FP32 tiles form each complex product with three real products (KARA):
+    // P1 = Re A Re Y, P2 = Im A Im Y, P3 = (Re A + Im A)(Re Y + Im Y),
+    // accumulated per output (C1, C2; C alone for CX) over its coupled terms,
+    // and Re C = P1 - P2, Im C = P3 - P1 - P2 at the end: 12 real products per
+    // quaternion output pair and k instead of 16 (3 instead of 4 for CX).
+    constexpr bool KARA = MODE == 0;
     constexpr int NOUT = CX ? 1 : 2;                  // complex outputs per tile
     constexpr int NACC = KARA ? 3 * NOUT : 4;
     v16f acc[NACC][MB][NB];
@@ -382,7 +378,6 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
         // A fragments of the chunk, read and formed once for all NB column blocks
         float xa[MODE == 0 ? MB : 1][4][8];
         V8 ah[MB][4], al[MB][4];
-        V8 ash[MB][2], asl[MB][2];                      // split fp16: sums Re + Im of A1, A2
         if constexpr (MODE == 0) {
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) load_a(b, mb, c, mask, xa[mb]);
@@ -399,15 +394,6 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                     load_a(b, mb, c, mask, xs);
 #pragma unroll
                     for (int pl = 0; pl < NPA; ++pl) split8<H>(xs[pl], ah[mb][pl], al[mb][pl]);
-                    if constexpr (KARA) {
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            float sum[8];
-#pragma unroll
-                            for (int j = 0; j < 8; ++j) sum[j] = 0.5f * (xs[2 * h][j] + xs[2 * h + 1][j]);
-                            split8<H>(sum, ash[mb][h], asl[mb][h]);
-                        }
-                    }
                 }
             }
         }
@@ -496,47 +482,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                         split8<H>(x, yh, yl);
                     }
                 };
-                if constexpr (MODE == 2 && KARA) {
-                    // three split products per complex product, pairs of staged
-                    // B planes as in the FP32 branch (fp16 scale sb on B).  The
-                    // sums are halved (exactly) so that they stay inside the fp16
-                    // range like the scaled operands; P3 is taken x 4 at the end.
-#pragma unroll
-                    for (int pp = 0; pp < 4; ++pp) {
-                        if (dma) {
-                            issue_slice(c + 1, 2 * pp);
-                            issue_slice(c + 1, 2 * pp + 1);
-                        }
-                        float yr[8], yi[8], ys[8];
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) {
-                            const int k = 8 * lg + j;
-                            const bool ok = col_ok && (!mask || (c * KT + k < a.n));
-                            const float vr = sm.B[b][2 * pp][k / RB][(k % RB) * NT + cl];
-                            const float vi = sm.B[b][2 * pp + 1][k / RB][(k % RB) * NT + cl];
-                            yr[j] = ok ? (pp == 2 ? -vr : vr) * sb : 0.f;
-                            yi[j] = ok ? (pp == 3 ? -vi : vi) * sb : 0.f;
-                            ys[j] = 0.5f * (yr[j] + yi[j]);
-                        }
-                        V8 yrh, yrl, yih, yil, ysh, ysl;
-                        split8<H>(yr, yrh, yrl);
-                        split8<H>(yi, yih, yil);
-                        split8<H>(ys, ysh, ysl);
-                        const int ca = (pp & 1) ? 3 : 0;
-                        const int apl = (pp & 2) ? 2 : 0;
-#pragma unroll
-                        for (int step = 0; step < 3; ++step)
-#pragma unroll
-                            for (int mb = 0; mb < MB; ++mb) {
-                                acc[ca][mb][nb] = mfma16<H>(step == 0 ? al[mb][apl] : ah[mb][apl],
-                                                            step == 1 ? yrl : yrh, acc[ca][mb][nb]);
-                                acc[ca + 1][mb][nb] = mfma16<H>(step == 0 ? al[mb][apl + 1] : ah[mb][apl + 1],
-                                                                step == 1 ? yil : yih, acc[ca + 1][mb][nb]);
-                                acc[ca + 2][mb][nb] = mfma16<H>(step == 0 ? asl[mb][apl / 2] : ash[mb][apl / 2],
-                                                                step == 1 ? ysl : ysh, acc[ca + 2][mb][nb]);
-                            }
-                    }
-                } else if constexpr (CX) {
+                if constexpr (CX) {
                     // complex: plane 0 (Re B) and plane 1 (Im B) of C1 alone
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
@@ -796,7 +742,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                         for (int r = 0; r < 16; ++r) {
                             const float p1 = acc[3 * h][mb][nb][r], p2 = acc[3 * h + 1][mb][nb][r];
                             out[2 * h][mb][nb][r] = p1 - p2;
-                            out[2 * h + 1][mb][nb][r] = P3F * acc[3 * h + 2][mb][nb][r] - p1 - p2;
+                            out[2 * h + 1][mb][nb][r] = acc[3 * h + 2][mb][nb][r] - p1 - p2;
                         }
             store_tile<MB, NB, 0, 2 * NOUT>(a, f, row0, col0, out, scale, lane);
         } else {
