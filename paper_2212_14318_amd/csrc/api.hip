@@ -164,6 +164,13 @@ int run_tprod(int m, int n, int s, int p, const T* A, const T* B, T* C, int prec
             float* partials = scales + 2 * (size_t)p;
             st = hip_status(qt::launch_fp16_scales(fa, partials, scales, stream));
             if (st != QT_OK) return st;
+            if (s > qt::kNarrowMaxS) {
+                // scaled fp16 words in place (narrow products read the FP32 values)
+                st = hip_status(qt::launch_fp16_words(Ah, p, m, n, lda, scales, stream));
+                if (st != QT_OK) return st;
+                st = hip_status(qt::launch_fp16_words(Bh, p, n, s, ldb, scales + p, stream));
+                if (st != QT_OK) return st;
+            }
             st = hip_status(qt::launch_facewise_f32(fa, prec, stream, qt::choose_tile(m, n, s, prec), scales));
             if (st != QT_OK) return st;
             FftJob<T> inv16[1] = {{Ch, C, m, s, ldc, s}};

@@ -63,10 +63,10 @@ __device__ __forceinline__ void store_tile(const FacewiseArgs<float>& a, int f, 
 // product X Y is taken as Xhi Yhi + Xhi Ylo + Xlo Yhi (the dropped Xlo Ylo is
 // ~2^-16 relative for bf16), each on v_mfma_f32_32x32x16_{bf16,f16} with FP32
 // accumulation.  The split operands take the same bytes in HBM as FP32 ones:
-// for bf16 the forward tube FFT writes every real as one word hi | lo << 16
-// and the fragments are unpacked with byte permutes; for fp16 the operands
-// stay FP32 (the scale depends on the whole frequency) and are scaled and
-// split when the fragments are formed.
+// every real is one word hi | lo << 16, unpacked into fragments with byte
+// permutes.  For bf16 the forward tube FFT writes the words; for fp16 a pass
+// after the per-frequency power-of-two scales writes them in place (the scale
+// depends on the whole frequency), and the product undoes the scales.
 //
 // The coupled products are rewritten as two plain complex products,
 //   C1^ = A1^ B1^[f] + A2^ D,  D = -conj(B2^[g]),
@@ -107,13 +107,13 @@ __device__ __forceinline__ V8 neg8(V8 x) {
 enum TileCfg { TILE_128x64 = 0, TILE_64x128 = 1, TILE_64x64 = 2, NUM_TILE_CFGS = 3 };
 __host__ __device__ constexpr int tile_mt(int cfg) { return cfg == TILE_128x64 ? 128 : 64; }
 __host__ __device__ constexpr int tile_nt(int cfg) { return cfg == TILE_64x128 ? 128 : 64; }
-// Every split-bf16 tile splits 8 waves into two plane groups (tile_v2's PG):
-// each wave reads half the staged planes per chunk, which cuts LDS fragment
-// reads and unpacking by a third.
-__host__ __device__ constexpr bool plane_groups(int mode, int cfg) { return mode == 1 && cfg >= 0; }
+// Every split tile (bf16 or fp16 words) splits 8 waves into two plane groups
+// (tile_v2's PG): each wave reads half the staged planes per chunk, which cuts
+// LDS fragment reads and unpacking by a third.
+__host__ __device__ constexpr bool plane_groups(int mode, int cfg) { return mode != 0 && cfg >= 0; }
 // Waves per workgroup of a tile shape and mode (0 FP32, 1 split bf16, 2 split
 // fp16): 8 waves for the 128 x 64 tile (4 x 2, each 32 x 32) and for every
-// split-bf16 tile (two plane groups of 2 x 2), so that two waves share a SIMD
+// split tile (two plane groups of 2 x 2), so that two waves share a SIMD
 // and hide each other's LDS and VALU latency; the other 64-wide tiles run 4
 // waves (2 x 2).  (A 64-wide tile stages 96 or 160 KB per workgroup, so one
 // workgroup fills a CU's LDS.)
@@ -145,8 +145,8 @@ __host__ __device__ constexpr int tile_waves(int mode, int cfg) {
 // MODE 1: operands already split by the tube FFT into bf16 words hi | lo << 16
 //         (FftJob::pack), unpacked with byte permutes, 3 products per term on
 //         v_mfma_f32_32x32x16_bf16 (one k-step per chunk);
-// MODE 2: FP32 operands scaled by powers of two and split into fp16 hi + lo
-//         when the fragments are formed, on v_mfma_f32_32x32x16_f16.
+// MODE 2: the same with fp16 words of operands scaled by powers of two per
+//         frequency (undone at the store), on v_mfma_f32_32x32x16_f16.
 typedef __attribute__((address_space(3))) void lds_void_t;
 
 // CX: complex products (two A planes, two B planes) instead of the coupled
@@ -161,18 +161,8 @@ __device__ __forceinline__ void dma16(const float* g, float* lds_block) {
     __builtin_amdgcn_global_load_lds((const void*)g, (lds_void_t*)lds_block, 16, 0, 0);
 }
 
-template <typename H>
-__device__ __forceinline__ void split8(const float (&x)[8], typename SplitTypes<H>::v8& hi,
-                                       typename SplitTypes<H>::v8& lo) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        hi[j] = (H)x[j];
-        lo[j] = (H)(x[j] - (float)hi[j]);
-    }
-}
-
-// Split-bf16 operand words (hi | lo << 16, written by the tube FFT) -> the
-// hi and lo fragments of 8 consecutive k (one v_perm_b32 per pair).
+// Split operand words (hi | lo << 16, bf16 or fp16) -> the hi and lo
+// fragments of 8 consecutive k (one v_perm_b32 per pair).
 template <typename V8>
 __device__ __forceinline__ void unpack8(const unsigned (&w)[8], V8& hi, V8& lo) {
     typedef unsigned u4 __attribute__((ext_vector_type(4)));
@@ -197,7 +187,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     // 1 the D, E planes with A2, and the partial sums meet once per tile.
     // CX: the complex product C^[f] = A^[f] B^[f] (A2 = B2 = 0: no coupling
     // with -f), two A planes, two B planes, output planes 0 and 1.
-    static_assert(!PG || (MODE == 1 && !CX), "plane groups are built for the split-bf16 quaternion path");
+    static_assert(!PG || (MODE != 0 && !CX), "plane groups are built for the split quaternion paths");
     constexpr int NPA = CX ? 2 : 4, NPB = CX ? 2 : 8;
     constexpr int WG = PG ? NW / 2 : NW;
     constexpr int WM = WG / 2;
@@ -333,7 +323,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const bool ok = row_ok && (!mask || (c * KT + 8 * lg + j < a.n));
-                x[pl][j] = ok ? (MODE == 2 ? v[j] * sa : v[j]) : 0.f;
+                x[pl][j] = ok ? v[j] : 0.f;
             }
         }
     };
@@ -384,17 +374,10 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
         } else {
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
-                if constexpr (MODE == 1) {
-                    unsigned wa[4][8];
-                    load_a_words(b, mb, c, mask, wa);
+                unsigned wa[4][8];
+                load_a_words(b, mb, c, mask, wa);
 #pragma unroll
-                    for (int pl = 0; pl < NPA; ++pl) unpack8(wa[pl], ah[mb][pl], al[mb][pl]);
-                } else {
-                    float xs[4][8];
-                    load_a(b, mb, c, mask, xs);
-#pragma unroll
-                    for (int pl = 0; pl < NPA; ++pl) split8<H>(xs[pl], ah[mb][pl], al[mb][pl]);
-                }
+                for (int pl = 0; pl < NPA; ++pl) unpack8(wa[pl], ah[mb][pl], al[mb][pl]);
             }
         }
 #pragma unroll
@@ -449,38 +432,23 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                 // all B words of the chunk are read up front, so that their LDS
                 // latency overlaps the products of the earlier planes
                 unsigned wb[8][8];
-                if constexpr (MODE == 1) {
 #pragma unroll
-                    for (int q = 0; q < NPB; ++q)
+                for (int q = 0; q < NPB; ++q)
 #pragma unroll
-                        for (int j = 0; j < 8; ++j) {
-                            const int k = 8 * lg + j;
-                            wb[q][j] = __builtin_bit_cast(unsigned, sm.B[b][q][k / RB][(k % RB) * NT + cl]);
-                        }
-                }
+                    for (int j = 0; j < 8; ++j) {
+                        const int k = 8 * lg + j;
+                        wb[q][j] = __builtin_bit_cast(unsigned, sm.B[b][q][k / RB][(k % RB) * NT + cl]);
+                    }
                 // B fragment (hi, lo) of staged plane q, D/E signs applied
                 auto bfrag = [&](int q, V8& yh, V8& yl) {
-                    if constexpr (MODE == 1) {
-                        const unsigned flip = (q == 4 || q == 7) ? 0x80008000u : 0u;
-                        unsigned w[8];
+                    const unsigned flip = (q == 4 || q == 7) ? 0x80008000u : 0u;
+                    unsigned w[8];
 #pragma unroll
-                        for (int j = 0; j < 8; ++j) {
-                            const bool ok = col_ok && (!mask || (c * KT + 8 * lg + j < a.n));
-                            w[j] = ok ? (wb[q][j] ^ flip) : 0u;
-                        }
-                        unpack8(w, yh, yl);
-                    } else {
-                        const float sgn = (q == 4 || q == 7) ? -sb : sb;
-                        float x[8];
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) {
-                            const int k = 8 * lg + j;
-                            const float v = sm.B[b][q][k / RB][(k % RB) * NT + cl];
-                            const bool ok = col_ok && (!mask || (c * KT + k < a.n));
-                            x[j] = ok ? v * sgn : 0.f;
-                        }
-                        split8<H>(x, yh, yl);
+                    for (int j = 0; j < 8; ++j) {
+                        const bool ok = col_ok && (!mask || (c * KT + 8 * lg + j < a.n));
+                        w[j] = ok ? (wb[q][j] ^ flip) : 0u;
                     }
+                    unpack8(w, yh, yl);
                 };
                 if constexpr (CX) {
                     // complex: plane 0 (Re B) and plane 1 (Im B) of C1 alone

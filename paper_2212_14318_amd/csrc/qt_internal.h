@@ -130,6 +130,10 @@ int get_twiddles(int p, hipStream_t stream, Twiddles* out);
 // In-place FP32 -> split-bf16 words of `faces` faces of rows x cols (row
 // stride ld, a multiple of 4).
 hipError_t launch_split_words(float* X, long faces, long rows, long cols, long ld, hipStream_t stream);
+// In place: the Fourier-domain tensor [4][p][rows][ld] (cols valid columns)
+// becomes fp16 words hi | lo << 16 of x * scale[f] (the split-fp16 operands).
+hipError_t launch_fp16_words(float* X, long p, long rows, long cols, long ld, const float* scale,
+                             hipStream_t stream);
 
 // Tile shape (detail::TileCfg) for one facewise product: from the autotuner's
 // cost model when it has run on this device for this precision, else the

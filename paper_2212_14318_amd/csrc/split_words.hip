@@ -36,7 +36,47 @@ split_words_kernel(float* __restrict__ X, long faces, long rows, long cols, long
     }
 }
 
+// fp16 words of a Fourier-domain tensor [4][p][rows][ld] scaled per
+// frequency: x -> hi | lo << 16 with hi = rn_fp16(x s_f), lo = rn_fp16(x s_f
+// - hi); s_f = scale[f] is a power of two, so the scaling is exact.
+__global__ void __launch_bounds__(256)
+fp16_words_kernel(float* __restrict__ X, long p, long rows, long cols, long ld, const float* __restrict__ scale) {
+    const long groups = (cols + 3) / 4;
+    const long total = 4 * p * rows * groups;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const long g = e % groups;
+        const long fr = e / groups;                      // (plane * p + face) * rows + row
+        const float sc = scale[(fr / rows) % p];
+        float* row = X + fr * ld + 4 * g;
+        const int n = (int)(cols - 4 * g < 4 ? cols - 4 * g : 4);
+        auto word = [sc](float x) {
+            const float y = x * sc;
+            const _Float16 hi = (_Float16)y;
+            const _Float16 lo = (_Float16)(y - (float)hi);
+            return (unsigned)__builtin_bit_cast(unsigned short, hi) |
+                   ((unsigned)__builtin_bit_cast(unsigned short, lo) << 16);
+        };
+        if (n == 4) {
+            const float4 v = *reinterpret_cast<const float4*>(row);
+            *reinterpret_cast<uint4*>(row) = uint4{word(v.x), word(v.y), word(v.z), word(v.w)};
+        } else {
+            for (int j = 0; j < n; ++j) reinterpret_cast<unsigned*>(row)[j] = word(row[j]);
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_fp16_words(float* X, long p, long rows, long cols, long ld, const float* scale,
+                             hipStream_t stream) {
+    const long total = 4 * p * rows * ((cols + 3) / 4);
+    if (total <= 0) return hipSuccess;
+    long blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fp16_words_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, X, p, rows, cols, ld,
+                       scale);
+    return hipGetLastError();
+}
 
 hipError_t launch_split_words(float* X, long faces, long rows, long cols, long ld, hipStream_t stream) {
     const long total = faces * rows * ((cols + 3) / 4);
