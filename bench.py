@@ -219,7 +219,28 @@ def main():
         except nat.QtError as e:
             log(f"[bench] precision {prec} not available: {e}")
             continue
-        stage_calls(prec_id, ev0)
+        try:
+            stage_calls(prec_id, ev0)
+        except nat.QtError as e:
+            # split fp16 needs per-call scales and has no staged entry points: time
+            # whole qt_tprod calls (no per-kernel split for this precision)
+            log(f"[bench] {prec}: staged path not available ({e}); timing whole qt_tprod calls")
+            del C_ref
+            for k in range(args.warmup):
+                Ak, Bk, Ck = bufs[k % nsets]
+                ops.tprod(Ak, Bk, precision=prec, out=Ck)
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+            for k in range(args.steps):
+                Ak, Bk, Ck = bufs[k % nsets]
+                ops.tprod(Ak, Bk, precision=prec, out=Ck)
+            torch.cuda.synchronize()
+            ms_step = (time.perf_counter() - t_start) * 1e3 / args.steps
+            results[prec] = dict(ms_per_step=ms_step, tflops_equiv=F / (ms_step * 1e-3) / 1e12,
+                                 C=bufs[(args.steps - 1) % nsets][2].cpu().numpy())
+            log(f"[bench] {prec}: {ms_step:.3f} ms/step  {results[prec]['tflops_equiv']:.1f} TFLOP/s-equiv"
+                f"  (whole qt_tprod)")
+            continue
         torch.cuda.synchronize()
         same = bool(torch.equal(C, C_ref))
         del C_ref
@@ -314,13 +335,14 @@ def main():
     head = precs[0] if precs[0] in results else next(iter(results))
     r = results[head]
     peak = PEAK_TFLOPS[head]
-    roof = {"bound": "mfma", "achieved": round(r["gemm_tflops"], 3), "peak": peak,
+    staged = "gemm_tflops" in r
+    roof = None if not staged else {"bound": "mfma", "achieved": round(r["gemm_tflops"], 3), "peak": peak,
             "unit": "TFLOP/s", "frac": round(r["gemm_tflops"] / peak, 4),
             "traffic": measured_traffic(args.workload, head),
             "kernel": "facewise coupled product (qt_fourier_tprod)",
             "algorithmic_flops_per_launch": f_gemm,
             "algorithmic_bytes_per_launch": 16.0 * p * (m * n + n * s + m * s)}
-    if head.startswith("split"):
+    if staged and head.startswith("split"):
         roof["issued_frac"] = round(3 * r["gemm_tflops"] / peak, 4)
     dtype = {"fp32": "f32", "split_bf16": "bf16x3-split/f32-acc", "split_fp16": "fp16x3-split/f32-acc",
              "fp64": "f64"}[head]
@@ -340,10 +362,11 @@ def main():
         "cpu_fft_baseline": cpu_fft,
         "per_precision": {k: {kk2: (float(f"{v:.5g}") if isinstance(v, float) else v)
                               for kk2, v in d.items()} for k, d in results.items()},
-        "fft_roofline": {"bound": "hbm", "fwd_achieved": round(r["fft_fwd_gbps"], 1),
-                         "inv_achieved": round(r["fft_inv_gbps"], 1), "peak": PEAK_HBM_GBPS,
-                         "unit": "GB/s", "fwd_frac": round(r["fft_fwd_gbps"] / PEAK_HBM_GBPS, 4),
-                         "inv_frac": round(r["fft_inv_gbps"] / PEAK_HBM_GBPS, 4)},
+        "fft_roofline": None if not staged else {
+            "bound": "hbm", "fwd_achieved": round(r["fft_fwd_gbps"], 1),
+            "inv_achieved": round(r["fft_inv_gbps"], 1), "peak": PEAK_HBM_GBPS,
+            "unit": "GB/s", "fwd_frac": round(r["fft_fwd_gbps"] / PEAK_HBM_GBPS, 4),
+            "inv_frac": round(r["fft_inv_gbps"] / PEAK_HBM_GBPS, 4)},
     }
     if "fp32" in results and head != "fp32":
         out["speedup_vs_fp32"] = round(results["fp32"]["ms_per_step"] / r["ms_per_step"], 3)
