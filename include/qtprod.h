@@ -83,29 +83,34 @@ typedef enum {
                            FP32 accumulate */
     QT_SPLIT_FP16 = 2,  /* as QT_SPLIT_BF16 with fp16 hi+lo; operands scaled by a
                            power of two per frequency (A^[f]) and per frequency
-                           pair (B^[f], B^[-f]) computed on the device; qt_tprod
-                           only (the other entry points return QT_ERR_UNSUPPORTED) */
+                           pair (B^[f], B^[-f]) computed on the device.  Served
+                           by qt_tprod only: the scales belong to one product's
+                           operands, so qt_fourier_tprod, qt_tprod_backward,
+                           qt_tprod_batched / qt_batched_plan_create,
+                           qt_tprod_complex and qt_tprod_real return
+                           QT_ERR_UNSUPPORTED for it */
     QT_FP64 = 3         /* every step in double (small problems, validation) */
 } qt_precision;
 
-/* Largest p served.  Every p in [1, QT_MAX_P] is supported by the single-
- * problem entry points: 7-smooth p (prime factors 2, 3, 5, 7) up to 128 (64
- * for QT_FP64) have register-resident tube FFTs, every other p goes through
- * Bluestein's algorithm (chirp tables in FP64 on the device).  The batched
- * path serves 7-smooth p <= 64. */
+/* Largest p served (QT_ERR_UNSUPPORTED above it).  Every p in [1, QT_MAX_P]
+ * is supported by the single-problem entry points: 7-smooth p (prime factors
+ * 2, 3, 5, 7) up to 128 (64 for QT_FP64) have register-resident tube FFTs,
+ * every other p goes through Bluestein's algorithm (chirp tables in FP64 on
+ * the device), whose length-M convolution (M the power of two >= 2p - 1) is
+ * held in one workgroup's LDS.  The batched path serves 7-smooth p <= 64. */
 #define QT_MAX_P 4096
 
 /* Library ABI version (major * 100 + minor). */
 int qt_version(void);
 
 /* Human-readable name of a status code (static string, never NULL). */
-const char* qt_status_string(int status);
+const char* qt_status_string(qt_status status);
 
 /* Create the plan (twiddle table, and Bluestein chirp spectrum when p needs
  * one) for p on the current device, on `stream`, and wait for it.  Optional:
  * compute calls do this lazily.  Returns QT_OK, QT_ERR_INVALID_ARG,
  * QT_ERR_UNSUPPORTED, QT_ERR_ALLOC or QT_ERR_HIP. */
-int qt_prepare(int p, hipStream_t stream);
+qt_status qt_prepare(int p, hipStream_t stream);
 
 /* Row stride (in reals) that qt_tprod uses for its Fourier-domain tensors:
  * cols rounded up to a multiple of 4.  Any ld >= cols that is a multiple of 4
@@ -128,8 +133,8 @@ int qt_fourier_ld(int cols);
  * hi | lo << 16 with hi = rn_bf16(x), lo = rn_bf16(x - hi) (same layout and
  * size); QT_SPLIT_FP16, and any split precision with inverse = 1, transform
  * floats like QT_FP32. */
-int qt_tube_fft(int rows, int cols, int p, const void* X, int ldx, void* Xh, int ldh,
-                int inverse, int precision, hipStream_t stream);
+qt_status qt_tube_fft(int rows, int cols, int p, const void* X, int ldx, void* Xh, int ldh,
+                int inverse, qt_precision precision, hipStream_t stream);
 
 /* Step 2 alone, for Fourier-domain-resident chains: for every frequency f,
  *   C1^[f] = A1^[f] B1^[f] - A2^[f] conj(B2^[-f]),
@@ -140,8 +145,8 @@ int qt_tube_fft(int rows, int cols, int p, const void* X, int ldx, void* Xh, int
  * ldc must be multiples of 4 (16-byte rows).  qt_tube_fft(inverse = 1) of Ch
  * is then A * B.  No workspace.  QT_SPLIT_FP16 needs per-call scales and is
  * served by qt_tprod only (QT_ERR_UNSUPPORTED here). */
-int qt_fourier_tprod(int m, int n, int s, int p, const void* Ah, int lda, const void* Bh,
-                     int ldb, void* Ch, int ldc, int precision, hipStream_t stream);
+qt_status qt_fourier_tprod(int m, int n, int s, int p, const void* Ah, int lda, const void* Bh,
+                     int ldb, void* Ch, int ldc, qt_precision precision, hipStream_t stream);
 
 /* In place: turn a Fourier-domain FP32 tensor Xh [4][p][rows][ld] (e.g. the
  * C^ written by qt_fourier_tprod) into the QT_SPLIT_BF16 operand format, the
@@ -152,20 +157,20 @@ int qt_fourier_tprod(int m, int n, int s, int p, const void* Ah, int lda, const 
  * transformed tensors is the transform of A * B, ready to be multiplied
  * again.  Columns beyond cols are untouched.  ld >= cols, a multiple of 4;
  * Xh 16-byte aligned.  Returns QT_OK, QT_ERR_INVALID_ARG or QT_ERR_HIP. */
-int qt_split_words(int rows, int cols, int p, void* Xh, int ld, hipStream_t stream);
+qt_status qt_split_words(int rows, int cols, int p, void* Xh, int ld, hipStream_t stream);
 
 /* Workspace bytes needed by qt_tprod for these sizes and precision
  * (0 if an argument is invalid).  Holds the Fourier-domain tensors
  * A^, B^ and C^ (row strides rounded up to a multiple of 4 reals). */
-size_t qt_workspace_size(int m, int n, int s, int p, int precision);
+size_t qt_workspace_size(int m, int n, int s, int p, qt_precision precision);
 
 /* C = A * B.  A: m x n x p, B: n x s x p, C: m x s x p (layout above; all
  * device pointers).  ws: device workspace of ws_bytes >= qt_workspace_size().
  * C is fully overwritten.  Definition: Section 2.4; algorithm: Algorithm 5.1
  * with Theorem 5.1. */
-int qt_tprod(int m, int n, int s, int p,
+qt_status qt_tprod(int m, int n, int s, int p,
              const void* A, const void* B, void* C,
-             int precision, void* ws, size_t ws_bytes, hipStream_t stream);
+             qt_precision precision, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* One problem of a batch: sizes and device pointers, same layout as above. */
 typedef struct {
@@ -176,9 +181,11 @@ typedef struct {
 } qt_problem;
 
 /* Workspace bytes for qt_tprod_batched over `count` problems (host array). */
-size_t qt_batched_workspace_size(int count, const qt_problem* probs, int precision);
+size_t qt_batched_workspace_size(int count, const qt_problem* probs, qt_precision precision);
 
-/* C_i = A_i * B_i for count independent problems of any sizes and p, in three
+/* C_i = A_i * B_i for count independent problems of any sizes (Section 2.4
+ * definition of each product), each by Algorithm 5.1 with the coupled
+ * facewise products of Theorem 5.1 / Remark 5.1, in three
  * phases: the forward tube FFT of every A_i, B_i (one launch per distinct p,
  * one workgroup per 256 tubes); the coupled facewise products of every
  * frequency and output tile (one persistent launch per tile shape, walking a
@@ -191,7 +198,7 @@ size_t qt_batched_workspace_size(int count, const qt_problem* probs, int precisi
  * The first call per device and precision runs the autotuner (allocates and
  * synchronises once).  Same arithmetic as qt_tprod per problem (tile shapes
  * may differ, hence rounding order).  For graph replays use the plan API. */
-int qt_tprod_batched(int count, const qt_problem* probs, int precision,
+qt_status qt_tprod_batched(int count, const qt_problem* probs, qt_precision precision,
                      void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Batched plan: the work lists of one batch, built once, with all launches of
@@ -206,15 +213,15 @@ typedef struct qt_batched_plan_s* qt_batched_plan;
  * capture + instantiate the graph.  Not capture-safe itself.  precision:
  * QT_FP32 or QT_SPLIT_BF16; every p must be 7-smooth and <= 64 (else
  * QT_ERR_UNSUPPORTED). */
-int qt_batched_plan_create(int count, const qt_problem* probs, int precision, void* ws,
+qt_status qt_batched_plan_create(int count, const qt_problem* probs, qt_precision precision, void* ws,
                            size_t ws_bytes, hipStream_t stream, qt_batched_plan* plan);
 
 /* Replay the plan on `stream` (one hipGraphLaunch): recomputes every C_i from
  * the current contents of A_i and B_i. */
-int qt_batched_plan_launch(qt_batched_plan plan, hipStream_t stream);
+qt_status qt_batched_plan_launch(qt_batched_plan plan, hipStream_t stream);
 
 /* Release the plan's graph (the caller's buffers are untouched). */
-int qt_batched_plan_destroy(qt_batched_plan plan);
+qt_status qt_batched_plan_destroy(qt_batched_plan plan);
 
 /* Run (or load from the file named by the environment variable
  * QT_TUNE_CACHE) the autotuner for `precision` on the current device: it times
@@ -223,11 +230,11 @@ int qt_batched_plan_destroy(qt_batched_plan plan);
  * batched tube FFT for every batched p.  Allocates scratch memory and
  * synchronises `stream`.  Single-problem calls then use the cost model for
  * their tile shape too. */
-int qt_autotune(int precision, hipStream_t stream);
+qt_status qt_autotune(qt_precision precision, hipStream_t stream);
 
 /* Workspace bytes needed by qt_tprod_complex (0 if an argument is invalid or
  * the precision is not QT_FP32 / QT_SPLIT_BF16). */
-size_t qt_complex_workspace_size(int m, int n, int s, int p, int precision);
+size_t qt_complex_workspace_size(int m, int n, int s, int p, qt_precision precision);
 
 /* T-product of complex tensors, the special case A2 = B2 = 0 of the
  * quaternion product (Algorithm 2.1 and Proposition 2.1 of the paper, the
@@ -240,12 +247,12 @@ size_t qt_complex_workspace_size(int m, int n, int s, int p, int precision);
  * for qt_tprod); QT_SPLIT_FP16 and QT_FP64 return QT_ERR_UNSUPPORTED.  A real
  * tensor is a complex one with a zero imaginary plane.  Same preconditions,
  * ownership and error behaviour as qt_tprod. */
-int qt_tprod_complex(int m, int n, int s, int p, const void* A, const void* B, void* C,
-                     int precision, void* ws, size_t ws_bytes, hipStream_t stream);
+qt_status qt_tprod_complex(int m, int n, int s, int p, const void* A, const void* B, void* C,
+                     qt_precision precision, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Workspace bytes needed by qt_tprod_real (0 if an argument is invalid or the
  * precision is not QT_FP32 / QT_SPLIT_BF16). */
-size_t qt_real_workspace_size(int m, int n, int s, int p, int precision);
+size_t qt_real_workspace_size(int m, int n, int s, int p, qt_precision precision);
 
 /* T-product of real tensors (Algorithm 2.1 of the paper on real input, the
  * T-product of Kilmer and Martin).  The DFT of a real tube is Hermitian,
@@ -256,11 +263,11 @@ size_t qt_real_workspace_size(int m, int n, int s, int p, int precision);
  * (device pointers, C fully overwritten).  precision: QT_FP32 or
  * QT_SPLIT_BF16; QT_SPLIT_FP16 and QT_FP64 return QT_ERR_UNSUPPORTED.  Same
  * preconditions, ownership and error behaviour as qt_tprod. */
-int qt_tprod_real(int m, int n, int s, int p, const void* A, const void* B, void* C,
-                  int precision, void* ws, size_t ws_bytes, hipStream_t stream);
+qt_status qt_tprod_real(int m, int n, int s, int p, const void* A, const void* B, void* C,
+                  qt_precision precision, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Workspace bytes needed by qt_tprod_backward. */
-size_t qt_backward_workspace_size(int m, int n, int s, int p, int precision);
+size_t qt_backward_workspace_size(int m, int n, int s, int p, qt_precision precision);
 
 /* Adjoints of C = A * B for an output gradient G (m x s x p):
  *   dA = G * B^H   (m x n x p),   dB = A^H * G   (n x s x p),
@@ -270,10 +277,10 @@ size_t qt_backward_workspace_size(int m, int n, int s, int p, int precision);
  * dA, dB may be NULL to skip it.  Computed in the Fourier domain with the
  * same frequency coupling as the forward product (bcirc(A * B) =
  * bcirc(A) bcirc(B), proof of Theorem 5.1). */
-int qt_tprod_backward(int m, int n, int s, int p,
+qt_status qt_tprod_backward(int m, int n, int s, int p,
                       const void* A, const void* B, const void* G,
                       void* dA, void* dB,
-                      int precision, void* ws, size_t ws_bytes, hipStream_t stream);
+                      qt_precision precision, void* ws, size_t ws_bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -70,6 +70,16 @@ std::unordered_map<PlanKey, Twiddles, PlanKeyHash> g_plans;
 }  // namespace
 
 namespace qt {
+bool find_twiddles(int p, Twiddles* out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lock(g_plan_mutex);
+    auto it = g_plans.find(PlanKey{dev, p});
+    if (it == g_plans.end()) return false;
+    *out = it->second;
+    return true;
+}
+
 int get_twiddles(int p, hipStream_t stream, Twiddles* out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return QT_ERR_HIP;
@@ -137,11 +147,15 @@ int hip_status(hipError_t e) {
     return e == hipErrorNotSupported ? QT_ERR_UNSUPPORTED : QT_ERR_HIP;
 }
 
+// given: a ready plan for p (the allocation-free entry point), else the
+// plan cache is used.
 template <typename T>
 int run_tprod(int m, int n, int s, int p, const T* A, const T* B, T* C, int prec, char* ws,
-              hipStream_t stream) {
+              hipStream_t stream, const Twiddles* given = nullptr) {
     Twiddles tw;
-    int st = get_plan(p, stream, &tw);
+    int st = QT_OK;
+    if (given) tw = *given;
+    else st = get_plan(p, stream, &tw);
     if (st != QT_OK) return st;
     const int lda = (int)qt::fourier_ld(n), ldb = (int)qt::fourier_ld(s), ldc = ldb;
     T* Ah = reinterpret_cast<T*>(ws);
@@ -269,8 +283,8 @@ extern "C" {
 
 int qt_version(void) { return 100; }
 
-const char* qt_status_string(int status) {
-    switch (status) {
+const char* qt_status_string(qt_status status) {
+    switch ((int)status) {
         case QT_OK: return "QT_OK";
         case QT_ERR_INVALID_ARG: return "QT_ERR_INVALID_ARG: invalid size, pointer, alignment, aliasing or workspace";
         case QT_ERR_UNSUPPORTED: return "QT_ERR_UNSUPPORTED: request not supported by this build";
@@ -280,17 +294,17 @@ const char* qt_status_string(int status) {
     }
 }
 
-int qt_prepare(int p, hipStream_t stream) {
+qt_status qt_prepare(int p, hipStream_t stream) {
     if (p < 1) return QT_ERR_INVALID_ARG;
     if (p > QT_MAX_P) return QT_ERR_UNSUPPORTED;
     Twiddles tw;
-    return get_plan(p, stream, &tw);
+    return qt::to_status(get_plan(p, stream, &tw));
 }
 
 int qt_fourier_ld(int cols) { return cols < 1 ? 0 : (int)qt::fourier_ld(cols); }
 
-int qt_tube_fft(int rows, int cols, int p, const void* X, int ldx, void* Xh, int ldh, int inverse,
-                int precision, hipStream_t stream) {
+qt_status qt_tube_fft(int rows, int cols, int p, const void* X, int ldx, void* Xh, int ldh, int inverse,
+                qt_precision precision, hipStream_t stream) {
     if (!valid_precision(precision)) return QT_ERR_INVALID_ARG;
     if (!dims_ok(rows, cols, p) || !X || !Xh || !aligned16(X) || !aligned16(Xh))
         return QT_ERR_INVALID_ARG;
@@ -302,7 +316,7 @@ int qt_tube_fft(int rows, int cols, int p, const void* X, int ldx, void* Xh, int
     if (!p_supported(p, precision)) return QT_ERR_UNSUPPORTED;
     Twiddles tw;
     int st = get_plan(p, stream, &tw);
-    if (st != QT_OK) return st;
+    if (st != QT_OK) return qt::to_status(st);
     hipError_t e;
     if (precision == QT_FP64) {
         FftJob<double> j{(const double*)X, (double*)Xh, rows, cols, ldx, ldh};
@@ -312,11 +326,11 @@ int qt_tube_fft(int rows, int cols, int p, const void* X, int ldx, void* Xh, int
         FftJob<float> j{(const float*)X, (float*)Xh, rows, cols, ldx, ldh, pack};
         e = qt::launch_tube_fft<float>(p, inverse != 0, &j, 1, tw, stream);
     }
-    return e == hipSuccess ? QT_OK : QT_ERR_HIP;
+    return qt::to_status(e == hipSuccess ? QT_OK : QT_ERR_HIP);
 }
 
-int qt_fourier_tprod(int m, int n, int s, int p, const void* Ah, int lda, const void* Bh, int ldb,
-                     void* Ch, int ldc, int precision, hipStream_t stream) {
+qt_status qt_fourier_tprod(int m, int n, int s, int p, const void* Ah, int lda, const void* Bh, int ldb,
+                     void* Ch, int ldc, qt_precision precision, hipStream_t stream) {
     if (!valid_precision(precision)) return QT_ERR_INVALID_ARG;
     if (!dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p)) return QT_ERR_INVALID_ARG;
     if (!Ah || !Bh || !Ch || !aligned16(Ah) || !aligned16(Bh) || !aligned16(Ch))
@@ -340,16 +354,16 @@ int qt_fourier_tprod(int m, int n, int s, int p, const void* Ah, int lda, const 
         e = qt::launch_facewise_f32(fa, precision, stream);
     }
     if (e == hipErrorNotSupported) return QT_ERR_UNSUPPORTED;
-    return e == hipSuccess ? QT_OK : QT_ERR_HIP;
+    return qt::to_status(e == hipSuccess ? QT_OK : QT_ERR_HIP);
 }
 
-int qt_split_words(int rows, int cols, int p, void* Xh, int ld, hipStream_t stream) {
+qt_status qt_split_words(int rows, int cols, int p, void* Xh, int ld, hipStream_t stream) {
     if (!dims_ok(rows, cols, p) || !Xh || !aligned16(Xh)) return QT_ERR_INVALID_ARG;
     if (ld < cols || (ld & 3) || !dims_ok(rows, ld, p)) return QT_ERR_INVALID_ARG;
-    return hip_status(qt::launch_split_words((float*)Xh, 4L * p, rows, cols, ld, stream));
+    return qt::to_status(hip_status(qt::launch_split_words((float*)Xh, 4L * p, rows, cols, ld, stream)));
 }
 
-size_t qt_workspace_size(int m, int n, int s, int p, int precision) {
+size_t qt_workspace_size(int m, int n, int s, int p, qt_precision precision) {
     if (!valid_precision(precision) || !dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p))
         return 0;
     size_t total = fourier_bytes(m, n, p, precision) + fourier_bytes(n, s, p, precision) +
@@ -360,31 +374,54 @@ size_t qt_workspace_size(int m, int n, int s, int p, int precision) {
     return total;
 }
 
-namespace {
-int tprod_ws(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision,
-             void* ws, size_t ws_bytes, hipStream_t stream) {
+}  // extern "C"
+
+namespace qt {
+// Arguments of qt_tprod other than the workspace.
+int check_tprod(int m, int n, int s, int p, const void* A, const void* B, const void* C,
+                int precision) {
     if (!valid_precision(precision)) return QT_ERR_INVALID_ARG;
     if (!dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p)) return QT_ERR_INVALID_ARG;
-    if (!A || !B || !C || !ws) return QT_ERR_INVALID_ARG;
-    if (!aligned16(A) || !aligned16(B) || !aligned16(C) || !aligned16(ws)) return QT_ERR_INVALID_ARG;
-    const size_t need = qt_workspace_size(m, n, s, p, precision);
-    if (ws_bytes < need) return QT_ERR_INVALID_ARG;
+    if (!A || !B || !C) return QT_ERR_INVALID_ARG;
+    if (!aligned16(A) || !aligned16(B) || !aligned16(C)) return QT_ERR_INVALID_ARG;
     const size_t cb = tensor_bytes(m, s, p, precision);
     if (overlaps(C, cb, A, tensor_bytes(m, n, p, precision)) ||
-        overlaps(C, cb, B, tensor_bytes(n, s, p, precision)) ||
-        overlaps(ws, need, A, tensor_bytes(m, n, p, precision)) ||
-        overlaps(ws, need, B, tensor_bytes(n, s, p, precision)) || overlaps(ws, need, C, cb))
+        overlaps(C, cb, B, tensor_bytes(n, s, p, precision)))
         return QT_ERR_INVALID_ARG;
-    if (!p_supported(p, precision)) return QT_ERR_UNSUPPORTED;
+    return QT_OK;
+}
+
+int dispatch_tprod(int m, int n, int s, int p, const void* A, const void* B, void* C,
+                   int precision, char* ws, hipStream_t stream, const Twiddles* given) {
     if (precision == QT_FP64)
         return run_tprod<double>(m, n, s, p, (const double*)A, (const double*)B, (double*)C, precision,
-                                 (char*)ws, stream);
-    return run_tprod<float>(m, n, s, p, (const float*)A, (const float*)B, (float*)C, precision,
-                            (char*)ws, stream);
+                                 ws, stream, given);
+    return run_tprod<float>(m, n, s, p, (const float*)A, (const float*)B, (float*)C, precision, ws,
+                            stream, given);
 }
+}  // namespace qt
+
+namespace {
+int tprod_ws(int m, int n, int s, int p, const void* A, const void* B, void* C, qt_precision precision,
+             void* ws, size_t ws_bytes, hipStream_t stream) {
+    int st = qt::check_tprod(m, n, s, p, A, B, C, precision);
+    if (st != QT_OK) return st;
+    if (!ws || !aligned16(ws)) return QT_ERR_INVALID_ARG;
+    const size_t need = qt_workspace_size(m, n, s, p, precision);
+    if (ws_bytes < need) return QT_ERR_INVALID_ARG;
+    if (overlaps(ws, need, A, tensor_bytes(m, n, p, precision)) ||
+        overlaps(ws, need, B, tensor_bytes(n, s, p, precision)) ||
+        overlaps(ws, need, C, tensor_bytes(m, s, p, precision)))
+        return QT_ERR_INVALID_ARG;
+    if (!p_supported(p, precision)) return QT_ERR_UNSUPPORTED;
+    return qt::dispatch_tprod(m, n, s, p, A, B, C, precision, (char*)ws, stream, nullptr);
+}
+
 }  // namespace
 
-int qt_tprod(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision,
+extern "C" {
+
+qt_status qt_tprod(int m, int n, int s, int p, const void* A, const void* B, void* C, qt_precision precision,
              void* ws, size_t ws_bytes, hipStream_t stream) {
     return qt::with_workspace(ws, ws_bytes, qt_workspace_size(m, n, s, p, precision), stream,
                               [&](void* w, size_t wb) { return tprod_ws(m, n, s, p, A, B, C, precision, w, wb, stream); });
@@ -397,7 +434,7 @@ namespace {
 // spectrum of a real tube is Hermitian).
 int cx_faces(int p, bool real) { return real ? p / 2 + 1 : p; }
 
-size_t cx_workspace(int m, int n, int s, int p, int precision, bool real) {
+size_t cx_workspace(int m, int n, int s, int p, qt_precision precision, bool real) {
     if ((precision != QT_FP32 && precision != QT_SPLIT_BF16) || !dims_ok(m, n, p) || !dims_ok(n, s, p) ||
         !dims_ok(m, s, p))
         return 0;
@@ -411,7 +448,7 @@ size_t cx_workspace(int m, int n, int s, int p, int precision, bool real) {
 
 // Forward transforms of A and B (two planes, or one real plane to a half
 // spectrum), the uncoupled per-frequency complex products, and the inverse.
-int run_cx(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision, void* ws,
+int run_cx(int m, int n, int s, int p, const void* A, const void* B, void* C, qt_precision precision, void* ws,
            size_t ws_bytes, bool real, hipStream_t stream) {
     if (precision != QT_FP32 && precision != QT_SPLIT_BF16) {
         return valid_precision(precision) ? QT_ERR_UNSUPPORTED : QT_ERR_INVALID_ARG;
@@ -431,7 +468,7 @@ int run_cx(int m, int n, int s, int p, const void* A, const void* B, void* C, in
     if (!p_supported(p, precision)) return QT_ERR_UNSUPPORTED;
     Twiddles tw;
     int st = get_plan(p, stream, &tw);
-    if (st != QT_OK) return st;
+    if (st != QT_OK) return qt::to_status(st);
     const int h = cx_faces(p, real);
     const int lda = (int)qt::fourier_ld(n), ldb = (int)qt::fourier_ld(s), ldc = ldb;
     char* w = (char*)ws;
@@ -448,34 +485,34 @@ int run_cx(int m, int n, int s, int p, const void* A, const void* B, void* C, in
     if (qt::launch_tube_fft<float>(p, false, fwd, 2, tw, stream) != hipSuccess) return QT_ERR_HIP;
     FacewiseArgs<float> fa{Ah, Bh, Ch, m, n, s, h, lda, ldb, ldc};
     st = hip_status(qt::launch_facewise_cx(fa, precision == QT_SPLIT_BF16 ? 1 : 0, stream));
-    if (st != QT_OK) return st;
+    if (st != QT_OK) return qt::to_status(st);
     FftJob<float> inv[1] = {{Ch, (float*)C, m, s, ldc, s, 0, 1, hf}};
     return hip_status(qt::launch_tube_fft<float>(p, true, inv, 1, tw, stream));
 }
 
 }  // namespace
 
-size_t qt_complex_workspace_size(int m, int n, int s, int p, int precision) {
+size_t qt_complex_workspace_size(int m, int n, int s, int p, qt_precision precision) {
     return cx_workspace(m, n, s, p, precision, false);
 }
 
-int qt_tprod_complex(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision,
+qt_status qt_tprod_complex(int m, int n, int s, int p, const void* A, const void* B, void* C, qt_precision precision,
                      void* ws, size_t ws_bytes, hipStream_t stream) {
     return qt::with_workspace(ws, ws_bytes, cx_workspace(m, n, s, p, precision, false), stream,
                               [&](void* w, size_t wb) { return run_cx(m, n, s, p, A, B, C, precision, w, wb, false, stream); });
 }
 
-size_t qt_real_workspace_size(int m, int n, int s, int p, int precision) {
+size_t qt_real_workspace_size(int m, int n, int s, int p, qt_precision precision) {
     return cx_workspace(m, n, s, p, precision, true);
 }
 
-int qt_tprod_real(int m, int n, int s, int p, const void* A, const void* B, void* C, int precision,
+qt_status qt_tprod_real(int m, int n, int s, int p, const void* A, const void* B, void* C, qt_precision precision,
                   void* ws, size_t ws_bytes, hipStream_t stream) {
     return qt::with_workspace(ws, ws_bytes, cx_workspace(m, n, s, p, precision, true), stream,
                               [&](void* w, size_t wb) { return run_cx(m, n, s, p, A, B, C, precision, w, wb, true, stream); });
 }
 
-size_t qt_backward_workspace_size(int m, int n, int s, int p, int precision) {
+size_t qt_backward_workspace_size(int m, int n, int s, int p, qt_precision precision) {
     if (!valid_precision(precision) || !dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p))
         return 0;
     return backward_layout(m, n, s, p, precision).total;
@@ -483,7 +520,7 @@ size_t qt_backward_workspace_size(int m, int n, int s, int p, int precision) {
 
 namespace {
 int backward_ws(int m, int n, int s, int p, const void* A, const void* B, const void* G,
-                void* dA, void* dB, int precision, void* ws, size_t ws_bytes, hipStream_t stream) {
+                void* dA, void* dB, qt_precision precision, void* ws, size_t ws_bytes, hipStream_t stream) {
     if (!valid_precision(precision)) return QT_ERR_INVALID_ARG;
     if (!dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p)) return QT_ERR_INVALID_ARG;
     if (!A || !B || !G || !ws) return QT_ERR_INVALID_ARG;
@@ -511,12 +548,12 @@ int backward_ws(int m, int n, int s, int p, const void* A, const void* B, const 
 }
 }  // namespace
 
-int qt_tprod_backward(int m, int n, int s, int p, const void* A, const void* B, const void* G,
-                      void* dA, void* dB, int precision, void* ws, size_t ws_bytes,
+qt_status qt_tprod_backward(int m, int n, int s, int p, const void* A, const void* B, const void* G,
+                      void* dA, void* dB, qt_precision precision, void* ws, size_t ws_bytes,
                       hipStream_t stream) {
     return qt::with_workspace(ws, ws_bytes, qt_backward_workspace_size(m, n, s, p, precision), stream,
                               [&](void* w, size_t wb) {
-                                  return backward_ws(m, n, s, p, A, B, G, dA, dB, precision, w, wb, stream);
+                                  return qt::to_status(backward_ws(m, n, s, p, A, B, G, dA, dB, precision, w, wb, stream));
                               });
 }
 

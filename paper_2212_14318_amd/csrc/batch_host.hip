@@ -520,13 +520,13 @@ struct qt_batched_plan_s {
 
 extern "C" {
 
-int qt_autotune(int precision, hipStream_t stream) {
+qt_status qt_autotune(qt_precision precision, hipStream_t stream) {
     if (precision != QT_FP32 && precision != QT_SPLIT_BF16) return QT_ERR_UNSUPPORTED;
     qt::TuneTable t;
-    return qt::ensure_tuned(precision, stream, &t);
+    return qt::to_status(qt::ensure_tuned(precision, stream, &t));
 }
 
-size_t qt_batched_workspace_size(int count, const qt_problem* probs, int precision) {
+size_t qt_batched_workspace_size(int count, const qt_problem* probs, qt_precision precision) {
     if (count < 1 || !probs) return 0;
     if (precision != QT_FP32 && precision != QT_SPLIT_BF16 && precision != QT_SPLIT_FP16 &&
         precision != QT_FP64)
@@ -538,27 +538,27 @@ size_t qt_batched_workspace_size(int count, const qt_problem* probs, int precisi
     return qt::desc_layout(count, probs).total;
 }
 
-int qt_tprod_batched(int count, const qt_problem* probs, int precision, void* ws, size_t ws_bytes,
+qt_status qt_tprod_batched(int count, const qt_problem* probs, qt_precision precision, void* ws, size_t ws_bytes,
                      hipStream_t stream) {
     return qt::with_workspace(ws, ws_bytes, qt_batched_workspace_size(count, probs, precision), stream,
                               [&](void* w, size_t wb) { return qt::run_batched(count, probs, precision, w, wb, stream); });
 }
 
-int qt_batched_plan_create(int count, const qt_problem* probs, int precision, void* ws, size_t ws_bytes,
+qt_status qt_batched_plan_create(int count, const qt_problem* probs, qt_precision precision, void* ws, size_t ws_bytes,
                            hipStream_t stream, qt_batched_plan* out) {
     if (!out) return QT_ERR_INVALID_ARG;
     *out = nullptr;
     qt::DescLayout L;
     int st = qt::validate(count, probs, precision, ws, ws_bytes, &L);
-    if (st != QT_OK) return st;
+    if (st != QT_OK) return qt::to_status(st);
     qt::TuneTable t;
     st = qt::ensure_tuned(precision, stream, &t);
-    if (st != QT_OK) return st;
+    if (st != QT_OK) return qt::to_status(st);
     qt::HostLists H;
     st = qt::build_lists(count, probs, precision, (char*)ws, L, t, stream, &H);
-    if (st != QT_OK) return st;
+    if (st != QT_OK) return qt::to_status(st);
     st = qt::upload(H, (char*)ws, L, stream);
-    if (st != QT_OK) return st;
+    if (st != QT_OK) return qt::to_status(st);
     if (hipStreamSynchronize(stream) != hipSuccess) return QT_ERR_HIP;
 
     hipStream_t cap = nullptr;
@@ -582,18 +582,18 @@ int qt_batched_plan_create(int count, const qt_problem* probs, int precision, vo
     return QT_OK;
 }
 
-int qt_batched_plan_launch(qt_batched_plan plan, hipStream_t stream) {
+qt_status qt_batched_plan_launch(qt_batched_plan plan, hipStream_t stream) {
     if (!plan || !plan->exec) return QT_ERR_INVALID_ARG;
-    return hipGraphLaunch(plan->exec, stream) == hipSuccess ? QT_OK : QT_ERR_HIP;
+    return qt::to_status(hipGraphLaunch(plan->exec, stream) == hipSuccess ? QT_OK : QT_ERR_HIP);
 }
 
-int qt_batched_plan_destroy(qt_batched_plan plan) {
+qt_status qt_batched_plan_destroy(qt_batched_plan plan) {
     if (!plan) return QT_ERR_INVALID_ARG;
     int st = QT_OK;
     if (plan->exec && hipGraphExecDestroy(plan->exec) != hipSuccess) st = QT_ERR_HIP;
     if (plan->graph && hipGraphDestroy(plan->graph) != hipSuccess) st = QT_ERR_HIP;
     delete plan;
-    return st;
+    return qt::to_status(st);
 }
 
 }  // extern "C"

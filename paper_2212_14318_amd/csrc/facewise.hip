@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(256) facewise_narrow_kernel(FacewiseArgs<float
 // and sb[f] for the eight B planes of the pair {f, -f}, chosen so that the
 // largest magnitude lands in [2^14, 2^15) (hi <= 65504 with room, lo keeps
 // 11 more bits).  Powers of two make the scaling exact; the product is
-// multiplied back by 1 / (sa sb).  Max-abs is a deterministic two-pass
+// multiplied back by 1 / sa and then by 1 / sb.  Max-abs is a deterministic two-pass
 // reduction (per-block partials, then one thread per frequency).
 __global__ void __launch_bounds__(256)
 absmax_partial_kernel(const float* __restrict__ X, int rows, int cols, int ld, int p, int nblk,
@@ -275,8 +275,12 @@ absmax_partial_kernel(const float* __restrict__ X, int rows, int cols, int ld, i
 __device__ __forceinline__ float pow2_scale(float mx) {
     if (!(mx > 0.f) || !isfinite(mx)) return 1.f;
     int e;
-    (void)frexpf(mx, &e);                 // mx < 2^e
-    return ldexpf(1.f, 15 - e);           // mx * scale < 2^15
+    (void)frexpf(mx, &e);                 // mx < 2^e, e in [-148, 128]
+    // mx * scale < 2^15; the exponent is capped at 126 so that the scale and
+    // its reciprocal are normal floats (only inputs below 2^-111 hit the cap,
+    // and they then land below 2^15 instead of in [2^14, 2^15))
+    const int k = 15 - e < 126 ? 15 - e : 126;
+    return ldexpf(1.f, k);
 }
 
 __global__ void fp16_scales_kernel(const float* __restrict__ pa, int nba, const float* __restrict__ pb,

@@ -36,7 +36,8 @@ constexpr int KT = 16;     // k-chunk depth
 // holds row 8 (r / 4) + 4 (l / 32) + (r % 4), column l % 32.
 template <int MB, int NB, int C0 = 0, int NC = 4>
 __device__ __forceinline__ void store_tile(const FacewiseArgs<float>& a, int f, int row0, int col0,
-                                           const v16f (&acc)[4][MB][NB], float scale, int lane) {
+                                           const v16f (&acc)[4][MB][NB], float scale, float scale2,
+                                           int lane) {
     const size_t pc = (size_t)a.p * a.m * a.ldc;
     float* Cf = a.Ch + (size_t)f * a.m * a.ldc;
     const int lr = lane & 31, lk = lane >> 5;
@@ -52,7 +53,7 @@ __device__ __forceinline__ void store_tile(const FacewiseArgs<float>& a, int f, 
                 if (row < a.m) {
 #pragma unroll
                     for (int c = C0; c < C0 + NC; ++c)
-                        Cf[c * pc + (size_t)row * a.ldc + col] = acc[c][mb][nb][r] * scale;
+                        Cf[c * pc + (size_t)row * a.ldc + col] = (acc[c][mb][nb][r] * scale) * scale2;
                 }
             }
     }
@@ -631,7 +632,9 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
     if (chunk_inside(0)) issue_fast(0, 0);
     else issue(0, 0);
     const int nfull = edge_tile ? 0 : a.n / KT;
-    const float scale = (MODE == 0) ? 1.f : 1.f / (sa * sb);
+    // undo the fp16 scales one at a time: each reciprocal is a normal power
+    // of two, while 1 / (sa sb) could leave the float range
+    const float ra = (MODE == 0) ? 1.f : 1.f / sa, rb = (MODE == 0) ? 1.f : 1.f / sb;
     // The k loop and the epilogue, for plane group G (a compile-time constant,
     // so register arrays are indexed statically; both groups run the same
     // sequence of barriers).
@@ -697,7 +700,7 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
 #pragma unroll
                         for (int r = 0; r < 16; ++r) acc[keep + c2][mb][nb][r] += theirs[(size_t)(idx++) * LANES + slot];
             __syncthreads();                 // LDS may be reused by the next tile
-            store_tile<MB, NB, keep, 2>(a, f, row0, col0, acc, scale, lane);
+            store_tile<MB, NB, keep, 2>(a, f, row0, col0, acc, ra, rb, lane);
         } else if constexpr (KARA) {
             v16f out[4][MB][NB];
 #pragma unroll
@@ -712,9 +715,9 @@ __device__ __forceinline__ void tile_v2(const FacewiseArgs<float>& a, int f, int
                             out[2 * h][mb][nb][r] = p1 - p2;
                             out[2 * h + 1][mb][nb][r] = acc[3 * h + 2][mb][nb][r] - p1 - p2;
                         }
-            store_tile<MB, NB, 0, 2 * NOUT>(a, f, row0, col0, out, scale, lane);
+            store_tile<MB, NB, 0, 2 * NOUT>(a, f, row0, col0, out, ra, rb, lane);
         } else {
-            store_tile<MB, NB, 0, CX ? 2 : 4>(a, f, row0, col0, acc, scale, lane);
+            store_tile<MB, NB, 0, CX ? 2 : 4>(a, f, row0, col0, acc, ra, rb, lane);
         }
     };
     if constexpr (PG) {

@@ -126,6 +126,16 @@ hipError_t launch_conj_transpose(const ConjTJob<T>* jobs, int njobs, hipStream_t
 // Twiddle table of p on the current device from the plan cache (created on
 // first use on `stream`, which is then synchronised once).  Returns a qt_status.
 int get_twiddles(int p, hipStream_t stream, Twiddles* out);
+// The cached plan of p on the current device, if there is one (no allocation).
+bool find_twiddles(int p, Twiddles* out);
+
+// qt_tprod's checks of everything but the workspace (a qt_status), and its
+// three steps on a workspace of qt_workspace_size() bytes with the plan
+// `given` (nullptr: the plan cache).
+int check_tprod(int m, int n, int s, int p, const void* A, const void* B, const void* C,
+                int precision);
+int dispatch_tprod(int m, int n, int s, int p, const void* A, const void* B, void* C,
+                   int precision, char* ws, hipStream_t stream, const Twiddles* given);
 
 // In-place FP32 -> split-bf16 words of `faces` faces of rows x cols (row
 // stride ld, a multiple of 4).

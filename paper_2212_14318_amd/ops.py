@@ -25,15 +25,35 @@ def _dtype(prec: int):
     return torch.float64 if prec == nat.QT_FP64 else torch.float32
 
 
-def _check_tensor(x: torch.Tensor, name: str, prec: int, planes: int = 4):
+def _check_shape(x: torch.Tensor, name: str, planes: int = 4, shape=None,
+                 min_last: int | None = None):
+    """The library only sees pointers, so every size is checked here.
+    shape: the full expected shape (None entries are free); min_last: lower
+    bound of the last dimension (a row stride)."""
     if not isinstance(x, torch.Tensor) or x.dim() != 4 or x.shape[0] != planes:
         raise ValueError(f"{name} must be a tensor of shape ({planes}, p, rows, cols)")
+    if shape is not None:
+        if any(want is not None and got != want for got, want in zip(tuple(x.shape), shape)):
+            want = tuple("*" if w is None else w for w in shape)
+            raise ValueError(f"{name} has shape {tuple(x.shape)}, expected shape {want}")
+    if min_last is not None and x.shape[3] < min_last:
+        raise ValueError(f"{name} has shape {tuple(x.shape)}: its last dimension must be at least "
+                         f"{min_last}")
+
+
+def _check_storage(x: torch.Tensor, name: str, prec: int):
     if x.device.type != "cuda":
         raise ValueError(f"{name} must live on a ROCm device")
     if x.dtype != _dtype(prec):
         raise ValueError(f"{name} must be {_dtype(prec)} for this precision, got {x.dtype}")
     if not x.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+
+
+def _check_all(prec: int, *named):
+    """Storage checks of several operands whose shapes were checked first."""
+    for x, name in named:
+        _check_storage(x, name, prec)
 
 
 def _stream(dev) -> int:
@@ -53,13 +73,17 @@ def tube_fft(X: torch.Tensor, inverse: bool = False, precision="fp32", cols=None
     transformed.  `out` may have a different (padded) last dimension.
     """
     prec = _prec(precision)
-    _check_tensor(X, "X", prec)
+    _check_shape(X, "X")
     _, p, rows, ldx = X.shape
-    cols = ldx if cols is None else cols
+    cols = ldx if cols is None else int(cols)
+    if not 1 <= cols <= ldx:
+        raise ValueError(f"cols must be in [1, {ldx}] for X of shape {tuple(X.shape)}")
+    if out is not None:
+        _check_shape(out, "out", shape=(4, p, rows, None), min_last=cols)
+        _check_storage(out, "out", prec)
+    _check_storage(X, "X", prec)
     if out is None:
         out = torch.empty_like(X)
-    else:
-        _check_tensor(out, "out", prec)
     st = nat.qt_tube_fft(rows, cols, p, X.data_ptr(), ldx, out.data_ptr(), out.shape[3],
                          int(bool(inverse)), prec, _stream(X.device))
     nat.check(st, "qt_tube_fft")
@@ -74,14 +98,16 @@ def fourier_tprod(Ah: torch.Tensor, Bh: torch.Tensor, n: int, s: int, precision=
     valid columns; returns Ch (4, p, m, ldc) with s valid columns.
     """
     prec = _prec(precision)
-    _check_tensor(Ah, "Ah", prec)
-    _check_tensor(Bh, "Bh", prec)
+    _check_shape(Ah, "Ah", min_last=n)
     _, p, m, lda = Ah.shape
+    _check_shape(Bh, "Bh", shape=(4, p, n, None), min_last=s)
     ldb = Bh.shape[3]
+    if out is not None:
+        _check_shape(out, "out", shape=(4, p, m, None), min_last=s)
+        _check_storage(out, "out", prec)
+    _check_all(prec, (Ah, "Ah"), (Bh, "Bh"))
     if out is None:
         out = torch.empty((4, p, m, ldb), dtype=Ah.dtype, device=Ah.device)
-    else:
-        _check_tensor(out, "out", prec)
     st = nat.qt_fourier_tprod(m, n, s, p, Ah.data_ptr(), lda, Bh.data_ptr(), ldb, out.data_ptr(),
                               out.shape[3], prec, _stream(Ah.device))
     nat.check(st, "qt_fourier_tprod")
@@ -91,9 +117,12 @@ def fourier_tprod(Ah: torch.Tensor, Bh: torch.Tensor, n: int, s: int, precision=
 def split_words(Xh: torch.Tensor, cols=None) -> torch.Tensor:
     """In place: Fourier-domain FP32 tensor (4, p, rows, ld) -> split-bf16
     operand words (the first `cols` columns, default ld); returns Xh."""
-    _check_tensor(Xh, "Xh", nat.QT_FP32)
+    _check_shape(Xh, "Xh")
     _, p, rows, ld = Xh.shape
-    cols = ld if cols is None else cols
+    cols = ld if cols is None else int(cols)
+    if not 1 <= cols <= ld:
+        raise ValueError(f"cols must be in [1, {ld}] for Xh of shape {tuple(Xh.shape)}")
+    _check_storage(Xh, "Xh", nat.QT_FP32)
     st = nat.qt_split_words(rows, cols, p, Xh.data_ptr(), ld, _stream(Xh.device))
     nat.check(st, "qt_split_words")
     return Xh
@@ -103,16 +132,16 @@ def tprod(A: torch.Tensor, B: torch.Tensor, precision="fp32", out: torch.Tensor 
           ws: torch.Tensor | None = None) -> torch.Tensor:
     """C = A * B (T-product of quaternion tensors) on the GPU."""
     prec = _prec(precision)
-    _check_tensor(A, "A", prec)
-    _check_tensor(B, "B", prec)
+    _check_shape(A, "A")
     _, p, m, n = A.shape
-    if B.shape[1] != p or B.shape[2] != n:
-        raise ValueError("B must be n x s x p with A m x n x p")
+    _check_shape(B, "B", shape=(4, p, n, None))
     s = B.shape[3]
+    if out is not None:
+        _check_shape(out, "out", shape=(4, p, m, s))
+        _check_storage(out, "out", prec)
+    _check_all(prec, (A, "A"), (B, "B"))
     if out is None:
         out = torch.empty((4, p, m, s), dtype=A.dtype, device=A.device)
-    else:
-        _check_tensor(out, "out", prec)
     need = nat.qt_workspace_size(m, n, s, p, prec)
     if ws is None or ws.numel() < need:
         ws = workspace(need, A.device)
@@ -127,18 +156,16 @@ def tprod_complex(A: torch.Tensor, B: torch.Tensor, precision="fp32", out: torch
     """C = A * B for complex tensors of shape (2, p, rows, cols) = (Re, Im):
     one uncoupled complex product per frequency ("fp32" or "split_bf16")."""
     prec = _prec(precision)
-    _check_tensor(A, "A", nat.QT_FP32, planes=2)
-    _check_tensor(B, "B", nat.QT_FP32, planes=2)
+    _check_shape(A, "A", planes=2)
     _, p, m, n = A.shape
-    if B.shape[1] != p or B.shape[2] != n:
-        raise ValueError("B must be n x s x p with A m x n x p")
+    _check_shape(B, "B", planes=2, shape=(2, p, n, None))
     s = B.shape[3]
+    if out is not None:
+        _check_shape(out, "out", planes=2, shape=(2, p, m, s))
+        _check_storage(out, "out", nat.QT_FP32)
+    _check_all(nat.QT_FP32, (A, "A"), (B, "B"))
     if out is None:
         out = torch.empty((2, p, m, s), dtype=A.dtype, device=A.device)
-    else:
-        _check_tensor(out, "out", nat.QT_FP32, planes=2)
-        if tuple(out.shape) != (2, p, m, s):
-            raise ValueError("out must have shape (2, p, m, s)")
     need = nat.qt_complex_workspace_size(m, n, s, p, prec)
     if ws is None or ws.numel() < need:
         ws = workspace(need, A.device)
@@ -156,18 +183,17 @@ def tprod_real(A: torch.Tensor, B: torch.Tensor, precision="fp32", out: torch.Te
     for x, name in ((A, "A"), (B, "B")):
         if not isinstance(x, torch.Tensor) or x.dim() != 3:
             raise ValueError(f"{name} must be a tensor of shape (p, rows, cols)")
-    _check_tensor(A.unsqueeze(0), "A", nat.QT_FP32, planes=1)
-    _check_tensor(B.unsqueeze(0), "B", nat.QT_FP32, planes=1)
     p, m, n = A.shape
-    if B.shape[0] != p or B.shape[1] != n:
-        raise ValueError("B must be n x s x p with A m x n x p")
+    _check_shape(B.unsqueeze(0), "B", planes=1, shape=(1, p, n, None))
     s = B.shape[2]
+    if out is not None:
+        if not isinstance(out, torch.Tensor) or out.dim() != 3:
+            raise ValueError("out must be a tensor of shape (p, m, s)")
+        _check_shape(out.unsqueeze(0), "out", planes=1, shape=(1, p, m, s))
+        _check_storage(out, "out", nat.QT_FP32)
+    _check_all(nat.QT_FP32, (A, "A"), (B, "B"))
     if out is None:
         out = torch.empty((p, m, s), dtype=A.dtype, device=A.device)
-    else:
-        _check_tensor(out.unsqueeze(0), "out", nat.QT_FP32, planes=1)
-        if tuple(out.shape) != (p, m, s):
-            raise ValueError("out must have shape (p, m, s)")
     need = nat.qt_real_workspace_size(m, n, s, p, prec)
     if ws is None or ws.numel() < need:
         ws = workspace(need, A.device)
@@ -181,12 +207,12 @@ def tprod_backward(A: torch.Tensor, B: torch.Tensor, G: torch.Tensor, precision=
                    need_dA: bool = True, need_dB: bool = True):
     """(dA, dB) = (G * B^H, A^H * G) on the GPU; None for a skipped one."""
     prec = _prec(precision)
-    for x, nm in ((A, "A"), (B, "B"), (G, "G")):
-        _check_tensor(x, nm, prec)
+    _check_shape(A, "A")
     _, p, m, n = A.shape
+    _check_shape(B, "B", shape=(4, p, n, None))
     s = B.shape[3]
-    if G.shape != (4, p, m, s):
-        raise ValueError("G must have the shape of A * B")
+    _check_shape(G, "G", shape=(4, p, m, s))
+    _check_all(prec, (A, "A"), (B, "B"), (G, "G"))
     dA = torch.empty_like(A) if need_dA else None
     dB = torch.empty_like(B) if need_dB else None
     need = nat.qt_backward_workspace_size(m, n, s, p, prec)
@@ -199,6 +225,15 @@ def tprod_backward(A: torch.Tensor, B: torch.Tensor, G: torch.Tensor, precision=
     return dA, dB
 
 
+def _check_problem(A, B, C, prec):
+    """One problem of a batch: A m x n x p, B n x s x p, C m x s x p."""
+    _check_shape(A, "A")
+    _, p, m, n = A.shape
+    _check_shape(B, "B", shape=(4, p, n, None))
+    _check_shape(C, "C", shape=(4, p, m, B.shape[3]))
+    _check_all(prec, (A, "A"), (B, "B"), (C, "C"))
+
+
 def tprod_batched(As, Bs, precision="fp32", outs=None):
     """[A_i * B_i] for lists of tensors in one call of the batched path
     (tube FFTs per distinct p, one persistent product launch per tile shape)."""
@@ -206,15 +241,18 @@ def tprod_batched(As, Bs, precision="fp32", outs=None):
     if len(As) != len(Bs) or not As:
         raise ValueError("need equally many A and B tensors (at least one)")
     items = []
+    if outs is not None and len(outs) != len(As):
+        raise ValueError("need one output tensor per problem")
+    for A, B in zip(As, Bs):
+        _check_shape(A, "A")
+        _check_shape(B, "B", shape=(4, A.shape[1], A.shape[3], None))
     if outs is None:
         outs = []
         for A, B in zip(As, Bs):
             outs.append(torch.empty((4, A.shape[1], A.shape[2], B.shape[3]), dtype=A.dtype,
                                     device=A.device))
     for A, B, C in zip(As, Bs, outs):
-        _check_tensor(A, "A", prec)
-        _check_tensor(B, "B", prec)
-        _check_tensor(C, "C", prec)
+        _check_problem(A, B, C, prec)
         items.append((A.shape[2], A.shape[3], B.shape[3], A.shape[1], A.data_ptr(), B.data_ptr(),
                       C.data_ptr()))
     probs = nat.make_problems(items)
@@ -234,14 +272,17 @@ class BatchedPlan:
         prec = _prec(precision)
         if len(As) != len(Bs) or not As:
             raise ValueError("need equally many A and B tensors (at least one)")
+        if outs is not None and len(outs) != len(As):
+            raise ValueError("need one output tensor per problem")
+        for A, B in zip(As, Bs):
+            _check_shape(A, "A")
+            _check_shape(B, "B", shape=(4, A.shape[1], A.shape[3], None))
         if outs is None:
             outs = [torch.empty((4, A.shape[1], A.shape[2], B.shape[3]), dtype=A.dtype,
                                 device=A.device) for A, B in zip(As, Bs)]
         items = []
         for A, B, C in zip(As, Bs, outs):
-            _check_tensor(A, "A", prec)
-            _check_tensor(B, "B", prec)
-            _check_tensor(C, "C", prec)
+            _check_problem(A, B, C, prec)
             items.append((A.shape[2], A.shape[3], B.shape[3], A.shape[1], A.data_ptr(),
                           B.data_ptr(), C.data_ptr()))
         self._keep = (list(As), list(Bs))
@@ -287,9 +328,13 @@ class QTProd(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, A, B, precision="fp32"):
+        if _prec(precision) == nat.QT_SPLIT_FP16 and any(ctx.needs_input_grad[:2]):
+            raise ValueError("split_fp16 has no backward (its per-frequency scales are made "
+                             "for one product); use fp32 or split_bf16 when gradients are needed")
         ctx.precision = precision
-        ctx.save_for_backward(A, B)
-        return tprod(A.contiguous(), B.contiguous(), precision)
+        A, B = A.contiguous(), B.contiguous()
+        ctx.save_for_backward(A, B)          # the contiguous tensors the backward needs
+        return tprod(A, B, precision)
 
     @staticmethod
     def backward(ctx, G):

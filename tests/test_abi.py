@@ -275,3 +275,35 @@ def test_batched_workspace_size_grows():
     two = nat.make_problems([(16, 16, 16, 8, A_, B_, C_), (200, 30, 70, 45, A_, B_, C_)])
     assert 0 < nat.qt_batched_workspace_size(1, one, F) < nat.qt_batched_workspace_size(2, two, F)
     assert nat.qt_batched_workspace_size(0, one, F) == 0
+
+
+_FAULT_CHILD = r"""
+import ctypes, sys
+sys.path.insert(0, {root!r})
+from paper_2212_14318_amd import _native as nat
+a, b, c = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20), ctypes.c_void_p(3 << 20)
+g, da, db = ctypes.c_void_p(4 << 20), ctypes.c_void_p(5 << 20), ctypes.c_void_p(6 << 20)
+probs = (nat.qt_problem * 1)(nat.qt_problem(4, 4, 4, 8, a, b, c))
+print(nat.qt_tprod(4, 4, 4, 8, a, b, c, nat.QT_FP32, None, 0, None),
+      nat.qt_tprod_complex(4, 4, 4, 8, a, b, c, nat.QT_FP32, None, 0, None),
+      nat.qt_tprod_real(4, 4, 4, 8, a, b, c, nat.QT_SPLIT_BF16, None, 0, None),
+      nat.qt_tprod_backward(4, 4, 4, 8, a, b, g, da, db, nat.QT_FP32, None, 0, None),
+      nat.qt_tprod_batched(1, probs, nat.QT_FP32, None, 0, None),
+      nat.qt_tprod(0, 4, 4, 8, a, b, c, nat.QT_FP32, None, 0, None))
+"""
+
+
+def test_injected_allocation_failure_returns_alloc():
+    """QTPROD_FAULT=alloc makes the library's own workspace allocation
+    (ws == NULL) fail: every one-shot product returns QT_ERR_ALLOC before any
+    HIP call, while argument errors keep QT_ERR_INVALID_ARG (they are checked
+    first).  Run in a child process: the variable is read once per process."""
+    import subprocess
+    import sys
+    env = dict(os.environ, QTPROD_FAULT="alloc")
+    out = subprocess.run([sys.executable, "-c", _FAULT_CHILD.format(root=ROOT)], env=env,
+                         capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    got = [int(x) for x in out.stdout.split()]
+    A = nat.QT_ERR_ALLOC
+    assert got == [A, A, A, A, A, nat.QT_ERR_INVALID_ARG]

@@ -82,6 +82,8 @@ def test_plan_replays_track_inputs(prec):
 
 @pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
 def test_c4_full_batch(prec):
+    """The 512-problem batch: 48 entries of every problem (computed one by one
+    from the definition), each problem held to the stated tolerance."""
     sizes = synth.batch_problem_sizes()
     As, Bs = [], []
     for i, (m, n, s, p) in enumerate(sizes):
@@ -96,12 +98,14 @@ def test_c4_full_batch(prec):
     worst = 0.0
     for i, (m, n, s, p) in enumerate(sizes):
         A, B = synth.batch_problem_inputs(i, int(m), int(n), int(s), int(p))
-        k = rng.integers(0, p, 6); r = rng.integers(0, m, 6); c = rng.integers(0, s, 6)
+        k = rng.integers(0, p, 48); r = rng.integers(0, m, 48); c = rng.integers(0, s, 48)
         ref = oracle.tprod_entries(A, B, k, r, c)
         got = to_np(Cs[i][:, k, r, c])
         d = float(np.sum((got - ref) ** 2)); e = float(np.sum(ref ** 2))
         num += d; den += e
         worst = max(worst, np.sqrt(d / e))
+        if i % 128 == 127:
+            print(f"c4 {prec}: {i + 1} problems checked", flush=True)
     err = np.sqrt(num / den)
     print(f"c4 {prec}: sampled rel err {err:.3e}, worst problem {worst:.3e}")
-    assert err <= TOLS[prec] and worst <= 4 * TOLS[prec]
+    assert err <= TOLS[prec] and worst <= TOLS[prec]

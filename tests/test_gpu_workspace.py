@@ -83,3 +83,37 @@ def test_batched_null_workspace():
     torch.cuda.synchronize()
     for C, ref in zip(Cs, refs):
         assert rel_err(to_np(C), ref) < 1e-5
+
+
+_FAULT_GPU_CHILD = r"""
+import sys
+sys.path.insert(0, {root!r})
+import torch
+from paper_2212_14318_amd import _native as nat
+dev = torch.device("cuda:0")
+A = torch.randn((4, 8, 20, 12), device=dev)
+B = torch.randn((4, 8, 12, 16), device=dev)
+C = torch.full((4, 8, 20, 16), 7.0, device=dev)
+st = nat.qt_tprod(20, 12, 16, 8, A.data_ptr(), B.data_ptr(), C.data_ptr(), nat.QT_FP32, None, 0,
+                  torch.cuda.current_stream(dev).cuda_stream)
+torch.cuda.synchronize()
+print(st, bool((C == 7.0).all()))
+"""
+
+
+def test_injected_allocation_failure_launches_nothing():
+    """With QTPROD_FAULT=alloc the ws == NULL call returns QT_ERR_ALLOC and
+    leaves the output untouched (no kernel ran); the same call without it
+    succeeds (test_tprod_null_workspace).  A child process, since the variable
+    is read once per process."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, QTPROD_FAULT="alloc")
+    print("child: qt_tprod with QTPROD_FAULT=alloc", flush=True)
+    out = subprocess.run([sys.executable, "-c", _FAULT_GPU_CHILD.format(root=root)], env=env,
+                         capture_output=True, text=True, timeout=240)
+    assert out.returncode == 0, out.stderr[-2000:]
+    st, untouched = out.stdout.split()[-2:]
+    assert int(st) == nat.QT_ERR_ALLOC and untouched == "True"

@@ -277,17 +277,22 @@ def test_real_case_is_algorithm_2_1(rng, p):
 # Fourier-domain forms: the paper's coupled form agrees, the naive one does not
 # ---------------------------------------------------------------------------
 
-def fourier_coupled(A, B):
-    """Plain FFT along faces, frequency f coupled with -f (mod p)."""
+def fourier_paper_convention(A, B):
+    """The paper's convention of the same product: the transform of conj X
+    (Theorem 4.4; the quaternion conjugate of X1 + X2 j is conj X1 - X2 j),
+    faces paired as i and p + 2 - i (1-based) in eqs. TC and TC2 of Remark
+    5.1, and the inverse transform of conj C^.  With 0-based f the partner
+    face p + 2 - i is -f mod p.  All faces at once."""
     A1, A2 = cd_planes(A)
     B1, B2 = cd_planes(B)
     F = lambda X: np.fft.fft(X, axis=0)
-    a1, a2, b1, b2 = F(A1), F(A2), F(B1), F(B2)
-    p = A.shape[1]
-    neg = (-np.arange(p)) % p
-    c1 = a1 @ b1 - a2 @ np.conj(b2[neg])
-    c2 = a1 @ b2 + a2 @ np.conj(b1[neg])
-    return from_cd(np.fft.ifft(c1, axis=0), np.fft.ifft(c2, axis=0))
+    a1, a2 = F(np.conj(A1)), -F(A2)
+    b1, b2 = F(np.conj(B1)), -F(B2)
+    r = (-np.arange(A.shape[1])) % A.shape[1]
+    c1 = a1[r] @ b1[r] - np.conj(a2) @ b2[r]
+    c2 = np.conj(a1[r]) @ b2 + a2 @ b1
+    # conj of (c1 + c2 j) is conj c1 - c2 j
+    return from_cd(np.fft.ifft(np.conj(c1), axis=0), -np.fft.ifft(c2, axis=0))
 
 
 def fourier_naive(A, B):
@@ -303,9 +308,12 @@ def fourier_naive(A, B):
 
 @pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 8, 12, 13])
 def test_coupled_fourier_forms_match_definition(rng, p):
+    """The plain-DFT coupled form (oracle.tprod_fft) and the paper's own
+    convention (conj-transform, faces i and p + 2 - i) both give the
+    definitional product."""
     A, B = rand_q(rng, p, 4, 3), rand_q(rng, p, 3, 5)
     ref = ot.tprod(A, B)
-    assert ot.rel_frob(fourier_coupled(A, B), ref) < 1e-13
+    assert ot.rel_frob(fourier_paper_convention(A, B), ref) < 1e-13
     assert ot.rel_frob(oracle.tprod_fft(A, B), ref) < 1e-13
 
 
@@ -411,6 +419,44 @@ def test_adjoint_dot_identity(rng):
 
 
 # ---------------------------------------------------------------------------
+# Error measure: relative Frobenius norm over all four components
+# ---------------------------------------------------------------------------
+
+def _rel_frob_pins_hold():
+    ok = True
+    ones = np.ones((4, 2, 3, 3))
+    ok &= abs(ot.rel_frob(ones, 2.0 * ones) - 0.5) < 1e-15
+    ref = np.zeros((4, 2, 2, 2))
+    ref[0, 0, 0, 0] = 3.0
+    ref[3, 1, 1, 1] = 4.0
+    E = np.zeros_like(ref)
+    E[1, 1, 0, 1] = 1.0
+    E[2, 1, 0, 1] = 2.0
+    E[3, 1, 0, 1] = 2.0
+    ok &= abs(ot.rel_frob(ref + E, ref) - 0.6) < 1e-15
+    # an error confined to one component still counts: 1 / 5 from plane 3 alone
+    E3 = np.zeros_like(ref)
+    E3[3, 0, 1, 0] = 1.0
+    ok &= abs(ot.rel_frob(ref + E3, ref) - 0.2) < 1e-15
+    ok &= ot.rel_frob(ref, ref) == 0.0
+    return bool(ok)
+
+
+def test_rel_frob_hand_values():
+    """||X - ref||_F / ||ref||_F, both norms over all four components: values
+    worked out by hand (1/2, 3/5, 1/5 and 0)."""
+    assert _rel_frob_pins_hold()
+
+
+def test_rel_frob_scale_invariant_and_symmetric_in_sign(rng):
+    X = rand_q(rng, 3, 4, 5)
+    ref = rand_q(rng, 3, 4, 5)
+    e = ot.rel_frob(X, ref)
+    assert abs(ot.rel_frob(7.0 * X, 7.0 * ref) - e) < 1e-14
+    assert abs(ot.rel_frob(2.0 * ref - X, ref) - e) < 1e-14      # error -E has the same norm
+
+
+# ---------------------------------------------------------------------------
 # Planted mistakes: the pins above must reject each of them
 # ---------------------------------------------------------------------------
 
@@ -425,6 +471,7 @@ def _pins_hold(rng):
     dA, dB = ot.adjoints(A, B, Z)
     lhs = float(np.sum(C * Z))
     ok &= abs(lhs - float(np.sum(A * dA))) < 1e-10 and abs(lhs - float(np.sum(B * dB))) < 1e-10
+    ok &= _rel_frob_pins_hold()
     return bool(ok)
 
 
@@ -469,12 +516,38 @@ def _mut_tconjT_no_reverse(X):
     return oq.qconjT(np.asarray(X, dtype=np.float64))
 
 
+def _mut_rel_frob_squared(X, ref):
+    # ||X - ref||^2 / ||ref||^2: a 1e-5 gate would then admit errors near 3e-3
+    X, ref = np.asarray(X, np.float64), np.asarray(ref, np.float64)
+    return float(oq.qnorm2(X - ref) / oq.qnorm2(ref))
+
+
+def _mut_rel_frob_no_denominator(X, ref):
+    X, ref = np.asarray(X, np.float64), np.asarray(ref, np.float64)
+    return float(np.sqrt(oq.qnorm2(X - ref)))
+
+
+def _mut_rel_frob_first_component(X, ref):
+    # only the real component a is compared
+    X, ref = np.asarray(X, np.float64), np.asarray(ref, np.float64)
+    return float(np.linalg.norm(X[0] - ref[0]) / np.linalg.norm(ref[0]))
+
+
+def _mut_rel_frob_max_abs(X, ref):
+    X, ref = np.asarray(X, np.float64), np.asarray(ref, np.float64)
+    return float(np.abs(X - ref).max() / np.abs(ref).max())
+
+
 @pytest.mark.parametrize("target,mutant", [
     ("qmatmul", _mut_qmatmul_sign),
     ("qmatmul", _mut_qmatmul_dropped),
     ("qmatmul", _mut_qmatmul_swapped),
     ("bcirc", _mut_bcirc_index),
     ("tconjT", _mut_tconjT_no_reverse),
+    ("rel_frob", _mut_rel_frob_squared),
+    ("rel_frob", _mut_rel_frob_no_denominator),
+    ("rel_frob", _mut_rel_frob_first_component),
+    ("rel_frob", _mut_rel_frob_max_abs),
 ])
 def test_planted_mistakes_are_caught(rng, monkeypatch, target, mutant):
     assert _pins_hold(rng)
