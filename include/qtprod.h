@@ -73,7 +73,8 @@ typedef enum {
     QT_ERR_INVALID_ARG = -1,  /* bad size, pointer, alignment, aliasing, workspace */
     QT_ERR_UNSUPPORTED = -2,  /* valid request this build cannot serve (e.g. p too large) */
     QT_ERR_ALLOC = -3,        /* device allocation failed (plan cache, or a workspace requested with ws == NULL) */
-    QT_ERR_HIP = -4           /* a HIP runtime call or kernel launch failed */
+    QT_ERR_HIP = -4,          /* a HIP runtime call or kernel launch failed */
+    QT_ERR_TOO_LARGE = -5     /* the problem does not fit the fixed scratch of qt_tprod_noalloc */
 } qt_status;
 
 typedef enum {
@@ -200,6 +201,29 @@ size_t qt_batched_workspace_size(int count, const qt_problem* probs, qt_precisio
  * may differ, hence rounding order).  For graph replays use the plan API. */
 qt_status qt_tprod_batched(int count, const qt_problem* probs, qt_precision precision,
                      void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Size of the device array that qt_tprod_noalloc uses as its workspace:
+ * 256 MiB, held on every device the library runs on until the process ends. */
+#define QT_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* qt_tprod without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments (minus the workspace), arithmetic, kernels and
+ * results as qt_tprod: the workspace is a library-owned device array of
+ * QT_NOALLOC_SCRATCH_BYTES per device instead of a caller buffer.  If the
+ * plan of p was created before (qt_prepare, or any earlier call with this p
+ * on this device), it is used; otherwise the twiddle (and Bluestein) tables
+ * are generated into the array behind the workspace on this call (for a
+ * Bluestein length that is an O(M^2) kernel: call qt_prepare first).
+ * Returns QT_ERR_TOO_LARGE, before any launch, when qt_workspace_size() plus
+ * those tables exceeds QT_NOALLOC_SCRATCH_BYTES; the other statuses as
+ * qt_tprod.  Every call on one device shares that device's array, which keeps
+ * the last call's contents: calls that overlap in time on one device (other
+ * streams, other host threads) race and give wrong results; calls on one
+ * stream are ordered and safe.  The first call on a device resolves the
+ * array's device address (a host-side lookup, no allocation). */
+qt_status qt_tprod_noalloc(int m, int n, int s, int p, const void* A, const void* B, void* C,
+                     qt_precision precision, hipStream_t stream);
 
 /* Batched plan: the work lists of one batch, built once, with all launches of
  * the three phases captured into one hipGraph.  The plan refers to the

@@ -16,6 +16,7 @@ QT_ERR_INVALID_ARG = -1
 QT_ERR_UNSUPPORTED = -2
 QT_ERR_ALLOC = -3
 QT_ERR_HIP = -4
+QT_ERR_TOO_LARGE = -5
 
 QT_FP32 = 0
 QT_SPLIT_BF16 = 1
@@ -23,6 +24,7 @@ QT_SPLIT_FP16 = 2
 QT_FP64 = 3
 
 QT_MAX_P = 4096
+QT_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 PRECISIONS = {"fp32": QT_FP32, "split_bf16": QT_SPLIT_BF16, "split_fp16": QT_SPLIT_FP16,
               "fp64": QT_FP64}
@@ -46,6 +48,7 @@ SIGNATURES = {
     "qt_split_words": (_I, [_I, _I, _I, _P, _I, _P]),
     "qt_workspace_size": (_SZ, [_I, _I, _I, _I, _I]),
     "qt_tprod": (_I, [_I, _I, _I, _I, _P, _P, _P, _I, _P, _SZ, _P]),
+    "qt_tprod_noalloc": (_I, [_I, _I, _I, _I, _P, _P, _P, _I, _P]),
     "qt_batched_workspace_size": (_SZ, [_I, ctypes.POINTER(qt_problem), _I]),
     "qt_tprod_batched": (_I, [_I, ctypes.POINTER(qt_problem), _I, _P, _SZ, _P]),
     "qt_batched_plan_create": (_I, [_I, ctypes.POINTER(qt_problem), _I, _P, _SZ, _P,
@@ -146,6 +149,10 @@ def qt_tprod(m, n, s, p, A, B, C, precision, ws, ws_bytes, stream=0) -> int:
     return lib().qt_tprod(m, n, s, p, A, B, C, precision, ws, ws_bytes, stream)
 
 
+def qt_tprod_noalloc(m, n, s, p, A, B, C, precision, stream=0) -> int:
+    return lib().qt_tprod_noalloc(m, n, s, p, A, B, C, precision, stream)
+
+
 def make_problems(items):
     """items: sequence of (m, n, s, p, A_ptr, B_ptr, C_ptr) -> ctypes array."""
     arr = (qt_problem * len(items))()
@@ -187,3 +194,4 @@ def qt_backward_workspace_size(m, n, s, p, precision) -> int:
 
 def qt_tprod_backward(m, n, s, p, A, B, G, dA, dB, precision, ws, ws_bytes, stream=0) -> int:
     return lib().qt_tprod_backward(m, n, s, p, A, B, G, dA, dB, precision, ws, ws_bytes, stream)
+

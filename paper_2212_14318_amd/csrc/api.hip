@@ -96,28 +96,16 @@ int get_twiddles(int p, hipStream_t stream, Twiddles* out) {
         return QT_ERR_ALLOC;
     }
     bool ok = qt::launch_twiddles(p, tw, stream) == hipSuccess;
-    if (ok && !qt::tube_fft_supported<double>(p)) {
-        // Bluestein tables in one allocation: 4 x 16 B and 4 x 8 B per entry
-        qt::BluesteinTables& bt = tw.blue;
-        bt.M = qt::bluestein_length(p);
-        const size_t n64 = 2 * (size_t)bt.M + (size_t)p + (size_t)bt.M / 2;
+    const size_t tb = qt::bluestein_tables_bytes(p);
+    if (ok && tb) {
         char* mem = nullptr;
-        if (hipMalloc((void**)&mem, n64 * (sizeof(double2) + sizeof(float2))) != hipSuccess) {
+        if (hipMalloc((void**)&mem, tb) != hipSuccess) {
             (void)hipFree(tw.f32);
             (void)hipFree(tw.f64);
             return QT_ERR_ALLOC;
         }
-        double2* d = reinterpret_cast<double2*>(mem);
-        bt.chirp64 = d; d += p;
-        bt.hat_fwd64 = d; d += bt.M;
-        bt.hat_inv64 = d; d += bt.M;
-        bt.twm64 = d; d += bt.M / 2;
-        float2* s32 = reinterpret_cast<float2*>(d);
-        bt.chirp32 = s32; s32 += p;
-        bt.hat_fwd32 = s32; s32 += bt.M;
-        bt.hat_inv32 = s32; s32 += bt.M;
-        bt.twm32 = s32;
-        ok = qt::launch_bluestein_tables(p, bt, stream) == hipSuccess;
+        qt::carve_bluestein_tables(p, mem, &tw.blue);
+        ok = qt::launch_bluestein_tables(p, tw.blue, stream) == hipSuccess;
     }
     if (!ok || hipStreamSynchronize(stream) != hipSuccess) {
         (void)hipFree(tw.f32);
@@ -290,6 +278,7 @@ const char* qt_status_string(qt_status status) {
         case QT_ERR_UNSUPPORTED: return "QT_ERR_UNSUPPORTED: request not supported by this build";
         case QT_ERR_ALLOC: return "QT_ERR_ALLOC: device allocation failed";
         case QT_ERR_HIP: return "QT_ERR_HIP: HIP runtime or launch error";
+        case QT_ERR_TOO_LARGE: return "QT_ERR_TOO_LARGE: problem exceeds the allocation-free scratch";
         default: return "unknown qt_status";
     }
 }

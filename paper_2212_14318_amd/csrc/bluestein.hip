@@ -208,6 +208,27 @@ int bluestein_length(int p) {
     return M;
 }
 
+size_t bluestein_tables_bytes(int p) {
+    if (tube_fft_supported<double>(p)) return 0;   // FP64 covers fewer lengths than FP32
+    const size_t M = (size_t)bluestein_length(p);
+    // chirp (p), two spectra (M each), half-length twiddles (M / 2), in FP64 and FP32
+    return (2 * M + (size_t)p + M / 2) * (sizeof(double2) + sizeof(float2));
+}
+
+void carve_bluestein_tables(int p, char* mem, BluesteinTables* bt) {
+    bt->M = bluestein_length(p);
+    double2* d = reinterpret_cast<double2*>(mem);
+    bt->chirp64 = d; d += p;
+    bt->hat_fwd64 = d; d += bt->M;
+    bt->hat_inv64 = d; d += bt->M;
+    bt->twm64 = d; d += bt->M / 2;
+    float2* f = reinterpret_cast<float2*>(d);
+    bt->chirp32 = f; f += p;
+    bt->hat_fwd32 = f; f += bt->M;
+    bt->hat_inv32 = f; f += bt->M;
+    bt->twm32 = f;
+}
+
 hipError_t launch_bluestein_tables(int p, const BluesteinTables& bt, hipStream_t stream) {
     const int n = bt.M > p ? bt.M : p;
     hipLaunchKernelGGL(bluestein_tables_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, p, bt.M,

@@ -56,6 +56,11 @@ struct Twiddles {
 };
 
 int bluestein_length(int p);
+// Bytes of the Bluestein tables of p in one buffer (0 when every precision
+// has a register-resident kernel for p), and the carving of such a buffer
+// into the tables of `bt` (M set from p).
+size_t bluestein_tables_bytes(int p);
+void carve_bluestein_tables(int p, char* mem, BluesteinTables* bt);
 hipError_t launch_bluestein_tables(int p, const BluesteinTables& bt, hipStream_t stream);
 template <typename T>
 hipError_t launch_bluestein(int p, bool inverse, const FftJob<T>* jobs, int njobs,

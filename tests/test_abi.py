@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     for st in (nat.QT_OK, nat.QT_ERR_INVALID_ARG, nat.QT_ERR_UNSUPPORTED, nat.QT_ERR_ALLOC,
-               nat.QT_ERR_HIP):
+               nat.QT_ERR_HIP, nat.QT_ERR_TOO_LARGE):
         s = nat.qt_status_string(st)
         assert s.startswith("QT_")
     assert "unknown" in nat.qt_status_string(12345)
@@ -98,6 +98,21 @@ def test_tprod_rejects_null_misaligned_aliased_and_small_ws():
     assert nat.qt_tprod(*ok, A_, B_, C_, nat.QT_FP32, B_, ws, None) == nat.QT_ERR_INVALID_ARG
     # unknown precision
     assert nat.qt_tprod(*ok, A_, B_, C_, 7, W_, ws, None) == nat.QT_ERR_INVALID_ARG
+
+
+def test_noalloc_rejects_bad_args_and_oversize_on_host():
+    ok = (8, 8, 8, 8)
+    F = nat.QT_FP32
+    assert nat.qt_tprod_noalloc(0, 8, 8, 8, A_, B_, C_, F, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_noalloc(*ok, None, B_, C_, F, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_noalloc(*ok, A_ + 4, B_, C_, F, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_noalloc(*ok, A_, B_, A_ + 256, F, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_noalloc(*ok, A_, B_, C_, 7, None) == nat.QT_ERR_INVALID_ARG
+    assert nat.qt_tprod_noalloc(8, 8, 8, nat.QT_MAX_P + 1, A_, B_, C_, F, None) == nat.QT_ERR_UNSUPPORTED
+    # 512^3, p = 32: 402 MB of workspace, beyond the fixed array
+    big = (512, 512, 512, 32)
+    assert nat.qt_workspace_size(*big, F) > nat.QT_NOALLOC_SCRATCH_BYTES
+    assert nat.qt_tprod_noalloc(*big, A_, B_, C_, F, None) == nat.QT_ERR_TOO_LARGE
 
 
 def test_tube_fft_rejects_bad_args():
