@@ -25,8 +25,12 @@ tproduct   : bcirc / unfold / fold, the definitional T-product, its sampled
              least-squares loss and its adjoints, error norms.
 fast       : the paper's FFT-based Algorithm 5.1 in FP64 (the CPU FFT-based
              version the benchmark times; pinned against the definition).
+tsvd       : the quaternion t-SVD A = U * S * V^H built on the frequency-pair
+             matrices that Theorem 5.1 makes multiplicative, and the singular
+             values of bcirc(A) from the definition.
 """
 from .fast import tprod_fft  # noqa: F401
+from . import tsvd  # noqa: F401  (module: tsvd.tsvd, tsvd.bcirc_singular_values)
 from .quaternion import qmul, qmatmul, qconj, qconjT, qnorm2  # noqa: F401
 from .tproduct import (  # noqa: F401
     bcirc,
