@@ -306,6 +306,39 @@ qt_status qt_tprod_backward(int m, int n, int s, int p,
                       void* dA, void* dB,
                       qt_precision precision, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Workspace bytes needed by qt_tsvd (0 if an argument is invalid, a size is
+ * beyond the limits below, or the precision is not QT_FP32 / QT_FP64). */
+size_t qt_tsvd_workspace_size(int m, int n, int p, qt_precision precision);
+
+/* Quaternion t-SVD A = U * S * V^H of A (m x n x p): U (m x m x p) and
+ * V (n x n x p) unitary tensors (U^H * U = U * U^H = identity), S (m x n x p)
+ * f-diagonal (every face diagonal; its entries have no j part).  The paper
+ * names T-product factorisations as the use of its block diagonalisation
+ * (Section 6); this one follows from Theorem 5.1 / Remark 5.1: the matrices
+ *   chi_f(X) = [[X1^[f], X2^[f]], [-conj X2^[-f], conj X1^[-f]]]
+ * (X1^, X2^ the tube DFTs of the complex parts) satisfy chi_f(A * B) =
+ * chi_f(A) chi_f(B) and chi_f(X^H) = chi_f(X)^*, and chi_-f follows from
+ * chi_f, so one SVD per frequency pair {f, -f} (f = 0 .. p/2) gives the
+ * factors.  For f != -f the singular values of chi_f(A) in descending order
+ * are placed alternately on f and -f (value 2i on entry i of S1^[f], value
+ * 2i + 1 on entry i of S1^[-f]); for f = -f (f = 0, p/2) chi_f(A) is the
+ * complex adjoint of a quaternion matrix and the factors keep that structure.
+ * Truncating S to its first r diagonal tubes then keeps the 2r largest
+ * singular values of every chi_f.  The singular values of bcirc(A) are the
+ * p * min(m, n) values of sigma.
+ * Layout: A, U, S, V as in the T-product ([4][p][rows][cols]); sigma (may be
+ * NULL): p x min(m, n) reals, sigma[f][i] = entry (i, i) of S1^[f], the tube
+ * DFT of S's diagonal.  U, S and V may each be NULL (not written).  All device
+ * pointers; outputs must not overlap A, each other or the workspace.
+ * precision: QT_FP32 or QT_FP64 (one-sided Jacobi in that precision; split
+ * precisions return QT_ERR_UNSUPPORTED).  Limits: min(m, n) <= 512,
+ * max(m, n) <= 1024, p <= QT_MAX_P (QT_ERR_UNSUPPORTED beyond).  U and V are
+ * not unique (phases, bases of repeated singular values and of null spaces);
+ * S is.  One workgroup per frequency pair; workspace as qt_tprod (ws == NULL
+ * allocates on the stream). */
+qt_status qt_tsvd(int m, int n, int p, const void* A, void* U, void* S, void* V, void* sigma,
+                  qt_precision precision, void* ws, size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

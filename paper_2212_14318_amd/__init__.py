@@ -11,9 +11,10 @@ Cayley-Dickson parts X1 = a + b i and X2 = c + d i.
     from paper_2212_14318_amd import tprod, qtprod
     C = tprod(A, B, precision="fp32")     # or "split_bf16", "fp64"
     C = qtprod(A, B)                      # differentiable (autograd.Function)
+    U, S, V, sigma = tsvd(A)              # quaternion t-SVD, A = U * S * V^H
 """
 from .ops import (BatchedPlan, QTProd, autotune, fourier_tprod, qtprod, split_words, tprod,  # noqa: F401
-                  tprod_backward, tprod_batched, tprod_complex, tprod_real, tube_fft)
+                  tprod_backward, tprod_batched, tprod_complex, tprod_real, tsvd, tube_fft)
 from ._native import PRECISIONS, QtError  # noqa: F401
 
-__all__ = ["tprod", "tprod_complex", "tprod_real", "tube_fft", "fourier_tprod", "split_words", "BatchedPlan", "autotune", "tprod_backward", "tprod_batched", "qtprod", "QTProd", "PRECISIONS", "QtError"]
+__all__ = ["tprod", "tprod_complex", "tprod_real", "tube_fft", "fourier_tprod", "split_words", "BatchedPlan", "autotune", "tprod_backward", "tprod_batched", "tsvd", "qtprod", "QTProd", "PRECISIONS", "QtError"]

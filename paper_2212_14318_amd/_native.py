@@ -62,6 +62,8 @@ SIGNATURES = {
     "qt_tprod_real": (_I, [_I, _I, _I, _I, _P, _P, _P, _I, _P, _SZ, _P]),
     "qt_backward_workspace_size": (_SZ, [_I, _I, _I, _I, _I]),
     "qt_tprod_backward": (_I, [_I, _I, _I, _I, _P, _P, _P, _P, _P, _I, _P, _SZ, _P]),
+    "qt_tsvd_workspace_size": (_SZ, [_I, _I, _I, _I]),
+    "qt_tsvd": (_I, [_I, _I, _I, _P, _P, _P, _P, _P, _I, _P, _SZ, _P]),
 }
 
 _lib = None
@@ -195,3 +197,10 @@ def qt_backward_workspace_size(m, n, s, p, precision) -> int:
 def qt_tprod_backward(m, n, s, p, A, B, G, dA, dB, precision, ws, ws_bytes, stream=0) -> int:
     return lib().qt_tprod_backward(m, n, s, p, A, B, G, dA, dB, precision, ws, ws_bytes, stream)
 
+
+def qt_tsvd_workspace_size(m, n, p, precision) -> int:
+    return lib().qt_tsvd_workspace_size(m, n, p, precision)
+
+
+def qt_tsvd(m, n, p, A, U, S, V, sigma, precision, ws, ws_bytes, stream=0) -> int:
+    return lib().qt_tsvd(m, n, p, A, U, S, V, sigma, precision, ws, ws_bytes, stream)

@@ -1,0 +1,540 @@
+// Quaternion t-SVD A = U * S * V^H (A m x n x p, U m x m x p and V n x n x p
+// unitary tensors, S f-diagonal), built on the block diagonalisation of
+// Theorem 4.4 and the coupled products of Theorem 5.1 / Remark 5.1.
+//
+// With X^1, X^2 the tube DFTs of the complex parts of X = X1 + X2 j, the
+// matrices
+//     chi_f(X) = [[ X^1[f], X^2[f] ], [ -conj X^2[-f], conj X^1[-f] ]]
+// multiply as chi_f(A * B) = chi_f(A) chi_f(B) (that is what the coupled
+// products TC / TC2 say) and chi_f(X^H) = chi_f(X)^*.  chi_-f(X) is J conj(
+// chi_f(X)) J^T, so one SVD per frequency pair {f, -f} gives the factors at
+// both frequencies:
+//   * f != -f: a complex SVD of chi_f(A) (2m x 2n).  Singular value 2i (in
+//     descending order) goes to diagonal entry i of S^1[f], value 2i + 1 to
+//     entry i of S^1[-f]; singular vectors to columns i and half + i.
+//   * f == -f (f = 0, and p/2 for even p): chi_f(A) is the complex adjoint of
+//     the quaternion matrix A^1[f] + A^2[f] j, and the factors must be too.
+//     A quaternion column is stored as its first complex column (x; y); the
+//     second is its partner (-conj y; conj x).
+//
+// Steps: the forward tube FFT of A (the kernels of the T-product), one
+// workgroup per frequency pair running a one-sided (Hestenes) Jacobi SVD on
+// the columns of chi_f(A) (or of chi_f(A)^* when m < n, so that columns are
+// the long side), an orthonormal completion of the left vectors where the
+// matrix is not square or singular, and inverse tube FFTs of U^, S^ and V^.
+// For quaternion columns a Jacobi step first turns the quaternion inner
+// product of the two columns real by right-multiplying one column by a unit
+// quaternion, then applies a real plane rotation; partners follow implicitly,
+// so the factors keep their quaternion structure.
+#include <math.h>
+
+#include "qt_internal.h"
+#include "workspace.h"
+#include "../../include/qtprod.h"
+
+namespace qt {
+namespace {
+
+constexpr int kThreads = 512;
+constexpr int kWaves = kThreads / 64;
+constexpr int kMaxMin = 512;      // min(m, n) served
+constexpr int kMaxMax = 1024;     // max(m, n) served
+constexpr int kMaxSweeps = 60;
+
+template <typename T> struct Cx;
+template <> struct Cx<float> { using type = float2; };
+template <> struct Cx<double> { using type = double2; };
+
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+    return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// conj(a) * b
+template <typename V> __device__ __forceinline__ V cmulc(V a, V b) {
+    return V{a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+template <typename V> __device__ __forceinline__ V cconj(V a) { return V{a.x, -a.y}; }
+template <typename V, typename T> __device__ __forceinline__ V cscale(V a, T s) { return V{a.x * s, a.y * s}; }
+template <typename V> __device__ __forceinline__ V cneg(V a) { return V{-a.x, -a.y}; }
+
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Accumulator type of the inner products: double for both precisions, so
+// that the cosine between two FP32 columns is known far below the stopping
+// threshold (a float sum over 2 max(m, n) terms carries rounding errors of
+// about that threshold, and the sweeps would keep rotating on noise).
+using Acc = double;
+
+template <typename T>
+struct TsvdArgs {
+    const T* Ah;            // Fourier-domain A, [4][p][m][lda]
+    T* Uh;                  // U^, [4][p][m][ldu]
+    T* Vh;                  // V^, [4][p][n][ldv]
+    T* sigma;               // [p][min(m, n)]: diagonal of S^1[f]
+    char* pairs;            // per-pair scratch, pair_bytes each
+    size_t pair_bytes;
+    int m, n, p, lda, ldu, ldv;
+};
+
+// Per-pair scratch layout (complex entries), for r = max(m, n), c = min(m, n):
+//   X   2c columns of 2r   (columns of chi_f(A) or chi_f(A)^*)
+//   Q   2c columns of 2c   (accumulated rotations)
+//   L   2r columns of 2r   (left vectors in rank order, then completed)
+//   W   2r + r coefficients of the completion
+template <typename T>
+size_t pair_scratch_bytes(int m, int n) {
+    const size_t r = m > n ? m : n, c = m > n ? n : m;
+    const size_t e = 2 * c * 2 * r + 2 * c * 2 * c + 2 * r * 2 * r + 3 * r;
+    return (e * sizeof(typename Cx<T>::type) + 255) & ~(size_t)255;
+}
+
+// Position of player q in round t of the circle method over nup players
+// (nup even): every pair of players meets once in nup - 1 rounds.
+__device__ __forceinline__ int circle(int q, int t, int nup) {
+    return q == 0 ? 0 : ((q - 1 + t) % (nup - 1)) + 1;
+}
+
+// Partner component k of a quaternion column x of 2h entries.
+template <typename V>
+__device__ __forceinline__ V partner_at(const V* x, int k, int h) {
+    return k < h ? cneg(cconj(x[k + h])) : cconj(x[k - h]);
+}
+
+// One Jacobi step on columns xi, xj (2h entries each) and their rotation
+// columns qi, qj (2hq entries), executed by one wave.  Returns true if a
+// rotation was applied.
+template <typename T, typename V>
+__device__ bool jacobi_pair(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool quat, T tol, Acc negl2, int lane) {
+    Acc al = 0, be = 0, g1r = 0, g1i = 0, g2r = 0, g2i = 0;
+    for (int k = lane; k < h; k += 64) {
+        const V a0 = xi[k], a1 = xi[k + h], b0 = xj[k], b1 = xj[k + h];
+        const Acc a0x = a0.x, a0y = a0.y, a1x = a1.x, a1y = a1.y;
+        const Acc b0x = b0.x, b0y = b0.y, b1x = b1.x, b1y = b1.y;
+        al += a0x * a0x + a0y * a0y + a1x * a1x + a1y * a1y;
+        be += b0x * b0x + b0y * b0y + b1x * b1x + b1y * b1y;
+        // x_i^* x_j
+        g1r += a0x * b0x + a0y * b0y + a1x * b1x + a1y * b1y;
+        g1i += a0x * b0y - a0y * b0x + a1x * b1y - a1y * b1x;
+        if (quat) {   // x_i^* partner(x_j), partner(x_j) = (-conj b1; conj b0)
+            g2r += -(a0x * b1x - a0y * b1y) + (a1x * b0x - a1y * b0y);
+            g2i += (a0x * b1y + a0y * b1x) - (a1x * b0y + a1y * b0x);
+        }
+    }
+    al = wave_sum(al);
+    be = wave_sum(be);
+    g1r = wave_sum(g1r);
+    g1i = wave_sum(g1i);
+    if (quat) {
+        g2r = wave_sum(g2r);
+        g2i = wave_sum(g2i);
+    }
+    // a column at rounding level of the whole matrix belongs to the null
+    // space: rotating it only stirs rounding errors (and never converges)
+    if (al <= negl2 || be <= negl2) return false;
+    const Acc gn = sqrt(g1r * g1r + g1i * g1i + g2r * g2r + g2i * g2i);
+    if (!(gn > (Acc)tol * sqrt(al * be))) return false;
+    // x_j <- x_j conj(e), e = gamma / |gamma| (a unit quaternion, or a complex
+    // phase when g2 = 0): afterwards x_i^* x_j = |gamma| is real
+    const V e1c = V{T(g1r / gn), T(-g1i / gn)}, e2c = V{T(g2r / gn), T(-g2i / gn)};
+    const Acc zeta = (be - al) / (2 * gn);
+    const Acc t = (zeta >= 0 ? Acc(1) : Acc(-1)) / (fabs(zeta) + sqrt(Acc(1) + zeta * zeta));
+    const Acc csd = Acc(1) / sqrt(Acc(1) + t * t);
+    const T cs = T(csd), sn = T(csd * t);
+    auto apply = [&](V* ci, V* cj, int hh) {
+        for (int k = lane; k < hh; k += 64) {
+            const V a0 = ci[k], a1 = ci[k + hh], b0 = cj[k], b1 = cj[k + hh];
+            V c0 = cmul(e1c, b0), c1 = cmul(e1c, b1);
+            if (quat) {
+                c0 = cadd(c0, cmul(e2c, cneg(cconj(b1))));
+                c1 = cadd(c1, cmul(e2c, cconj(b0)));
+            }
+            ci[k] = csub(cscale(a0, cs), cscale(c0, sn));
+            ci[k + hh] = csub(cscale(a1, cs), cscale(c1, sn));
+            cj[k] = cadd(cscale(a0, sn), cscale(c0, cs));
+            cj[k + hh] = cadd(cscale(a1, sn), cscale(c1, cs));
+        }
+    };
+    apply(xi, xj, h);
+    apply(qi, qj, hq);
+    return true;
+}
+
+// Write column vector u (2*half entries, the slot-th column of chi_f(Y) for an
+// half x half quaternion tensor Y) into Y^ at frequencies f and g = -f:
+//   slot j <  half: Y^1[f](:, j) = top,        Y^2[g](:, j) = -conj(bottom)
+//   slot j >= half: Y^2[f](:, j - half) = top, Y^1[g](:, j - half) = conj(bottom)
+template <typename T, typename V>
+__device__ void write_slot(T* Yh, int ld, int p, int half, int f, int g, int slot, const V* u, int tid,
+                           int nthreads) {
+    const size_t plane = (size_t)p * half * ld;
+    const bool second = slot >= half;
+    const int j = second ? slot - half : slot;
+    for (int i = tid; i < half; i += nthreads) {
+        const V top = u[i], bot = u[i + half];
+        const V tf = top;
+        const V bg = second ? cconj(bot) : cneg(cconj(bot));
+        const int pf = second ? 2 : 0, pg = second ? 0 : 2;
+        const size_t rf = ((size_t)f * half + i) * ld + j, rg = ((size_t)g * half + i) * ld + j;
+        Yh[pf * plane + rf] = tf.x;
+        Yh[(pf + 1) * plane + rf] = tf.y;
+        Yh[pg * plane + rg] = bg.x;
+        Yh[(pg + 1) * plane + rg] = bg.y;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) tsvd_pair_kernel(TsvdArgs<T> a) {
+    using V = typename Cx<T>::type;
+    __shared__ T s_sig[2 * kMaxMin];
+    __shared__ int s_perm[2 * kMaxMin];
+    __shared__ unsigned char s_ok[2 * kMaxMax];
+    __shared__ V s_w[2 * kMaxMax];
+    __shared__ Acc s_red[kWaves];
+    __shared__ int s_flag;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int f = blockIdx.x, p = a.p, m = a.m, n = a.n;
+    const int g = (p - f) % p;
+    const bool quat = f == g;
+    const bool tall = m >= n;
+    const int r = tall ? m : n, c = tall ? n : m;
+    const int nu = quat ? c : 2 * c;       // Jacobi units (columns, or quaternion columns)
+    const int nL = quat ? r : 2 * r;       // left-side slots
+    const int R = 2 * r, Rq = 2 * c;
+    V* X = reinterpret_cast<V*>(a.pairs + (size_t)f * a.pair_bytes);
+    V* Q = X + (size_t)2 * c * R;
+    V* L = Q + (size_t)2 * c * Rq;
+    V* coef = L + (size_t)2 * r * R;
+    V* coef2 = coef + (size_t)2 * r;
+
+    const size_t pl = (size_t)p * m * a.lda;
+    auto A1 = [&](int fr, int i, int j) {
+        const size_t o = ((size_t)fr * m + i) * a.lda + j;
+        return V{a.Ah[o], a.Ah[pl + o]};
+    };
+    auto A2 = [&](int fr, int i, int j) {
+        const size_t o = ((size_t)fr * m + i) * a.lda + j;
+        return V{a.Ah[2 * pl + o], a.Ah[3 * pl + o]};
+    };
+    // entry k of unit u of the matrix whose columns are orthogonalised
+    auto entry = [&](int u, int k) -> V {
+        if (tall) {   // column u of chi_f(A)
+            if (u < n) return k < m ? A1(f, k, u) : cneg(cconj(A2(g, k - m, u)));
+            return k < m ? A2(f, k, u - n) : cconj(A1(g, k - m, u - n));
+        }
+        // column u of chi_f(A)^*: the conjugate of row u of chi_f(A)
+        if (u < m) return k < n ? cconj(A1(f, u, k)) : cconj(A2(f, u, k - n));
+        return k < n ? cneg(A2(g, u - m, k)) : A1(g, u - m, k - n);
+    };
+
+    // scale the pair's matrix by a power of two so that its largest entry is
+    // in [0.5, 1): the squared norms of the Jacobi steps then neither
+    // overflow nor underflow
+    T mx = 0;
+    for (int e = tid; e < nu * R; e += kThreads) {
+        const V v = entry(e / R, e % R);
+        mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0) s_red[wave] = mx;
+    __syncthreads();
+    mx = 0;
+    for (int w = 0; w < kWaves; ++w) mx = fmax(mx, (T)s_red[w]);
+    const int ex = (mx > 0 && isfinite(mx)) ? ilogb(mx) + 1 : 0;
+    const T scale = ldexp(T(1), -ex);
+    Acc fro = 0;
+    for (int e = tid; e < nu * R; e += kThreads) {
+        const V v = cscale(entry(e / R, e % R), scale);
+        X[e] = v;
+        fro += (Acc)v.x * v.x + (Acc)v.y * v.y;
+    }
+    for (int e = tid; e < nu * Rq; e += kThreads) Q[e] = V{(e % Rq) == (e / Rq) ? T(1) : T(0), T(0)};
+    fro = wave_sum(fro);
+    __syncthreads();
+    if (lane == 0) s_red[wave] = fro;
+    __syncthreads();
+    fro = 0;
+    for (int w = 0; w < kWaves; ++w) fro += s_red[w];
+
+    // one-sided Jacobi sweeps, round-robin over disjoint unit pairs.  tol:
+    // the largest cosine left between two columns; negl: the norm below which
+    // a column is rounding noise of the whole matrix (sum of squares fro)
+    const T eps = sizeof(T) == 4 ? T(5.9604645e-8) : T(1.1102230246251565e-16);
+    const T tol = eps * sqrt((T)R);
+    const Acc negl2 = (Acc)tol * tol * fro;
+    const int nup = nu + (nu & 1);
+    for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+        __syncthreads();
+        if (tid == 0) s_flag = 0;
+        __syncthreads();
+        for (int t = 0; t < nup - 1; ++t) {
+            for (int q = wave; q < nup / 2; q += kWaves) {
+                const int i = circle(q, t, nup), j = circle(nup - 1 - q, t, nup);
+                if (i >= nu || j >= nu) continue;
+                if (jacobi_pair<T, V>(X + (size_t)i * R, X + (size_t)j * R, Q + (size_t)i * Rq,
+                                      Q + (size_t)j * Rq, r, c, quat, tol, negl2, lane) &&
+                    lane == 0)
+                    s_flag = 1;
+            }
+            __syncthreads();
+        }
+        if (s_flag == 0) break;
+    }
+
+    // singular values (column norms) and their descending order
+    for (int u = wave; u < nu; u += kWaves) {
+        Acc s = 0;
+        for (int k = lane; k < R; k += 64) {
+            const V v = X[(size_t)u * R + k];
+            s += (Acc)v.x * v.x + (Acc)v.y * v.y;
+        }
+        s = wave_sum(s);
+        if (lane == 0) s_sig[u] = (T)sqrt(s);
+    }
+    __syncthreads();
+    for (int u = tid; u < nu; u += kThreads) {
+        const T su = s_sig[u];
+        int rank = 0;
+        for (int v = 0; v < nu; ++v) {
+            const T sv = s_sig[v];
+            rank += (sv > su) || (sv == su && v < u);
+        }
+        s_perm[rank] = u;
+    }
+    for (int k = tid; k < nL; k += kThreads) s_ok[k] = 0;
+    __syncthreads();
+
+    // sigma, and the normalised left vectors in rank order; a column at the
+    // noise level leaves its slot to the completion below
+    const T tiny = (T)sqrt(negl2);
+    for (int rho = tid; rho < nu; rho += kThreads) {
+        const T sv = s_sig[s_perm[rho]] / scale;
+        const int k = quat ? rho : rho / 2;
+        const int fr = (quat || !(rho & 1)) ? f : g;
+        a.sigma[(size_t)fr * c + k] = sv;
+    }
+    for (int rho = wave; rho < nu; rho += kWaves) {
+        const int u = s_perm[rho];
+        const T su = s_sig[u];
+        if (su > tiny) {
+            const T inv = T(1) / su;
+            for (int k = lane; k < R; k += 64) L[(size_t)rho * R + k] = cscale(X[(size_t)u * R + k], inv);
+            if (lane == 0) s_ok[rho] = 1;
+        }
+    }
+    __syncthreads();
+
+    // complete the left vectors to an orthonormal basis: Gram-Schmidt
+    // (twice) of unit vectors against the accepted columns (and, for
+    // quaternion columns, their partners).  A candidate is accepted when its
+    // residual exceeds half the average that must remain, which some
+    // candidate always does.
+    const T accept = T(0.5) / (T)R;
+    int cand = 0;
+    for (int rho = 0; rho < nL; ++rho) {
+        if (s_ok[rho]) continue;
+        while (cand < R) {
+            for (int k = tid; k < R; k += kThreads) s_w[k] = V{k == cand ? T(1) : T(0), T(0)};
+            __syncthreads();
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int b = tid; b < nL; b += kThreads) {
+                    if (!s_ok[b]) continue;
+                    const V* lb = L + (size_t)b * R;
+                    V d1 = V{0, 0}, d2 = V{0, 0};
+                    for (int k = 0; k < R; ++k) {
+                        const V w = s_w[k];
+                        d1 = cadd(d1, cmulc(lb[k], w));
+                        if (quat) d2 = cadd(d2, cmulc(partner_at(lb, k, r), w));
+                    }
+                    coef[b] = d1;
+                    if (quat) coef2[b] = d2;
+                }
+                __syncthreads();
+                for (int k = tid; k < R; k += kThreads) {
+                    V w = s_w[k];
+                    for (int b = 0; b < nL; ++b) {
+                        if (!s_ok[b]) continue;
+                        const V* lb = L + (size_t)b * R;
+                        w = csub(w, cmul(lb[k], coef[b]));
+                        if (quat) w = csub(w, cmul(partner_at(lb, k, r), coef2[b]));
+                    }
+                    s_w[k] = w;
+                }
+                __syncthreads();
+            }
+            Acc s = 0;
+            for (int k = tid; k < R; k += kThreads) s += (Acc)s_w[k].x * s_w[k].x + (Acc)s_w[k].y * s_w[k].y;
+            s = wave_sum(s);
+            if (lane == 0) s_red[wave] = s;
+            __syncthreads();
+            s = 0;
+            for (int w = 0; w < kWaves; ++w) s += s_red[w];
+            ++cand;
+            if (s > accept) {
+                const T inv = T(1 / sqrt(s));
+                for (int k = tid; k < R; k += kThreads) L[(size_t)rho * R + k] = cscale(s_w[k], inv);
+                __syncthreads();
+                if (tid == 0) s_ok[rho] = 1;
+                __syncthreads();
+                break;
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+
+    // place the vectors: rank rho goes to slot rho (quaternion columns) or
+    // to slot rho / 2 (+ half for odd rho) -- the interleaving of f and -f
+    T* Lh = tall ? a.Uh : a.Vh;
+    T* Qh = tall ? a.Vh : a.Uh;
+    const int ldl = tall ? a.ldu : a.ldv, ldq = tall ? a.ldv : a.ldu;
+    auto slot = [&](int rho, int half) { return quat ? rho : rho / 2 + ((rho & 1) ? half : 0); };
+    for (int rho = 0; rho < nL; ++rho)
+        write_slot<T, V>(Lh, ldl, p, r, f, g, slot(rho, r), L + (size_t)rho * R, tid, kThreads);
+    for (int rho = 0; rho < nu; ++rho)
+        write_slot<T, V>(Qh, ldq, p, c, f, g, slot(rho, c), Q + (size_t)s_perm[rho] * Rq, tid, kThreads);
+}
+
+// S^ from sigma: S^1[f](i, i) = sigma[f][i], every other entry zero.
+template <typename T>
+__global__ void __launch_bounds__(256) tsvd_sigma_kernel(const T* __restrict__ sigma, T* __restrict__ Sh, int m, int n,
+                                                         int p, int ld) {
+    const int k = m < n ? m : n;
+    const long total = 4L * p * m * ld;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const int j = (int)(e % ld);
+        const long rest = e / ld;
+        const int i = (int)(rest % m);
+        const long pf = rest / m;          // plane * p + face
+        const int f = (int)(pf % p), plane = (int)(pf / p);
+        Sh[e] = (plane == 0 && i == j && i < k) ? sigma[(size_t)f * k + i] : T(0);
+    }
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+bool aligned16(const void* ptr) { return ((uintptr_t)ptr & 15u) == 0; }
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+    if (!a || !b) return false;
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+struct TsvdLayout {
+    size_t ah, uh, vh, sh, sig, pairs, pair_bytes, total;
+};
+
+TsvdLayout tsvd_layout(int m, int n, int p, int prec) {
+    const size_t es = prec == QT_FP64 ? 8 : 4;
+    TsvdLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t b) { const size_t o = off; off += align_up(b); return o; };
+    L.ah = take(4 * (size_t)p * m * fourier_ld(n) * es);
+    L.uh = take(4 * (size_t)p * m * fourier_ld(m) * es);
+    L.vh = take(4 * (size_t)p * n * fourier_ld(n) * es);
+    L.sh = take(4 * (size_t)p * m * fourier_ld(n) * es);
+    L.sig = take((size_t)p * (m < n ? m : n) * es);
+    L.pair_bytes = prec == QT_FP64 ? pair_scratch_bytes<double>(m, n) : pair_scratch_bytes<float>(m, n);
+    L.pairs = take((size_t)(p / 2 + 1) * L.pair_bytes);
+    L.total = off;
+    return L;
+}
+
+bool tsvd_dims_ok(int m, int n, int p) {
+    return m >= 1 && n >= 1 && p >= 1 && p <= QT_MAX_P && (m < n ? m : n) <= kMaxMin &&
+           (m > n ? m : n) <= kMaxMax;
+}
+
+template <typename T>
+int run_tsvd(int m, int n, int p, const T* A, T* U, T* S, T* V, T* sigma_out, int prec, char* ws,
+             hipStream_t stream) {
+    Twiddles tw;
+    int st = get_twiddles(p, stream, &tw);
+    if (st != QT_OK) return st;
+    const TsvdLayout L = tsvd_layout(m, n, p, prec);
+    T* Ah = reinterpret_cast<T*>(ws + L.ah);
+    T* Uh = reinterpret_cast<T*>(ws + L.uh);
+    T* Vh = reinterpret_cast<T*>(ws + L.vh);
+    T* Sh = reinterpret_cast<T*>(ws + L.sh);
+    T* sig = sigma_out ? sigma_out : reinterpret_cast<T*>(ws + L.sig);
+    const int lda = (int)fourier_ld(n), ldu = (int)fourier_ld(m), ldv = (int)fourier_ld(n);
+
+    FftJob<T> fwd[1] = {{A, Ah, m, n, n, lda, 0}};
+    if (launch_tube_fft<T>(p, false, fwd, 1, tw, stream) != hipSuccess) return QT_ERR_HIP;
+    TsvdArgs<T> args{Ah, Uh, Vh, sig, ws + L.pairs, L.pair_bytes, m, n, p, lda, ldu, ldv};
+    hipLaunchKernelGGL(tsvd_pair_kernel<T>, dim3(p / 2 + 1), dim3(kThreads), 0, stream, args);
+    if (hipGetLastError() != hipSuccess) return QT_ERR_HIP;
+    if (S) {
+        const long total = 4L * p * m * lda;
+        const int blocks = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+        hipLaunchKernelGGL(tsvd_sigma_kernel<T>, dim3(blocks), dim3(256), 0, stream, sig, Sh, m, n, p, lda);
+        if (hipGetLastError() != hipSuccess) return QT_ERR_HIP;
+    }
+    FftJob<T> inv[3];
+    int ninv = 0;
+    if (U) inv[ninv++] = FftJob<T>{Uh, U, m, m, ldu, m};
+    if (V) inv[ninv++] = FftJob<T>{Vh, V, n, n, ldv, n};
+    if (S) inv[ninv++] = FftJob<T>{Sh, S, m, n, lda, n};
+    for (int q = 0; q < ninv; q += 2) {
+        if (launch_tube_fft<T>(p, true, inv + q, ninv - q < 2 ? ninv - q : 2, tw, stream) != hipSuccess)
+            return QT_ERR_HIP;
+    }
+    return QT_OK;
+}
+
+int tsvd_ws(int m, int n, int p, const void* A, void* U, void* S, void* V, void* sigma, qt_precision prec,
+            void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (prec != QT_FP32 && prec != QT_FP64 && prec != QT_SPLIT_BF16 && prec != QT_SPLIT_FP16)
+        return QT_ERR_INVALID_ARG;
+    if (m < 1 || n < 1 || p < 1 || !A || !aligned16(A)) return QT_ERR_INVALID_ARG;
+    const size_t es = prec == QT_FP64 ? 8 : 4;
+    const void* outs[4] = {U, S, V, sigma};
+    const size_t k = m < n ? m : n;
+    const size_t osz[4] = {4 * (size_t)p * m * m * es, 4 * (size_t)p * m * n * es, 4 * (size_t)p * n * n * es,
+                           (size_t)p * k * es};
+    const size_t abytes = 4 * (size_t)p * m * n * es;
+    for (int q = 0; q < 4; ++q) {
+        if (outs[q] && !aligned16(outs[q])) return QT_ERR_INVALID_ARG;
+        if (overlaps(outs[q], osz[q], A, abytes)) return QT_ERR_INVALID_ARG;
+        for (int o = 0; o < q; ++o)
+            if (overlaps(outs[q], osz[q], outs[o], osz[o])) return QT_ERR_INVALID_ARG;
+    }
+    if (prec != QT_FP32 && prec != QT_FP64) return QT_ERR_UNSUPPORTED;
+    if (!tsvd_dims_ok(m, n, p)) return QT_ERR_UNSUPPORTED;
+    const TsvdLayout L = tsvd_layout(m, n, p, prec);
+    if (!ws || !aligned16(ws) || ws_bytes < L.total) return QT_ERR_INVALID_ARG;
+    for (int q = 0; q < 4; ++q)
+        if (overlaps(outs[q], osz[q], ws, L.total)) return QT_ERR_INVALID_ARG;
+    if (overlaps(A, abytes, ws, L.total)) return QT_ERR_INVALID_ARG;
+    if (!U && !S && !V && !sigma) return QT_OK;
+    if (prec == QT_FP64)
+        return run_tsvd<double>(m, n, p, (const double*)A, (double*)U, (double*)S, (double*)V, (double*)sigma,
+                                prec, (char*)ws, stream);
+    return run_tsvd<float>(m, n, p, (const float*)A, (float*)U, (float*)S, (float*)V, (float*)sigma, prec,
+                           (char*)ws, stream);
+}
+
+}  // namespace
+}  // namespace qt
+
+extern "C" {
+
+size_t qt_tsvd_workspace_size(int m, int n, int p, qt_precision precision) {
+    if ((precision != QT_FP32 && precision != QT_FP64) || !qt::tsvd_dims_ok(m, n, p)) return 0;
+    return qt::tsvd_layout(m, n, p, precision).total;
+}
+
+qt_status qt_tsvd(int m, int n, int p, const void* A, void* U, void* S, void* V, void* sigma,
+                  qt_precision precision, void* ws, size_t ws_bytes, hipStream_t stream) {
+    return qt::with_workspace(ws, ws_bytes, qt_tsvd_workspace_size(m, n, p, precision), stream,
+                              [&](void* w, size_t wb) {
+                                  return qt::tsvd_ws(m, n, p, A, U, S, V, sigma, precision, w, wb, stream);
+                              });
+}
+
+}  // extern "C"

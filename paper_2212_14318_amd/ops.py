@@ -319,6 +319,32 @@ def autotune(precision="fp32", device=None):
     nat.check(nat.qt_autotune(_prec(precision), _stream(dev)), "qt_autotune")
 
 
+def tsvd(A: torch.Tensor, precision="fp32", ws: torch.Tensor | None = None):
+    """Quaternion t-SVD A = U * S * V^H on the GPU.
+
+    A: (4, p, m, n).  Returns (U (4, p, m, m), S (4, p, m, n), V (4, p, n, n),
+    sigma (p, min(m, n))), sigma[f, i] being entry (i, i) of S1^[f].
+    precision: "fp32" or "fp64"."""
+    prec = _prec(precision)
+    _check_shape(A, "A")
+    _, p, m, n = A.shape
+    _check_storage(A, "A", prec)
+    opts = dict(dtype=A.dtype, device=A.device)
+    U = torch.empty((4, p, m, m), **opts)
+    S = torch.empty((4, p, m, n), **opts)
+    V = torch.empty((4, p, n, n), **opts)
+    sigma = torch.empty((p, min(m, n)), **opts)
+    need = nat.qt_tsvd_workspace_size(m, n, p, prec)
+    if need == 0:     # split precisions, or sizes beyond the limits
+        nat.check(nat.QT_ERR_UNSUPPORTED, "qt_tsvd")
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, A.device)
+    st = nat.qt_tsvd(m, n, p, A.data_ptr(), U.data_ptr(), S.data_ptr(), V.data_ptr(), sigma.data_ptr(),
+                     prec, ws.data_ptr(), ws.numel(), _stream(A.device))
+    nat.check(st, "qt_tsvd")
+    return U, S, V, sigma
+
+
 class QTProd(torch.autograd.Function):
     """C = A * B with the hand-written Fourier-domain backward.
 

@@ -1,0 +1,154 @@
+"""GPU quaternion t-SVD (qt_tsvd) against the FP64 oracle.
+
+U and V are not unique, so they are checked by what they must satisfy:
+A = U * S * V^H and U^H * U = I = V^H * V through the oracle's definitional
+T-product.  S and sigma are unique (up to rounding) and are compared with the
+oracle's entry by entry.
+
+Tolerances.  The one-sided Jacobi stops rotating a pair of columns when their
+cosine is below sqrt(2 max(m, n)) u (u the unit roundoff), so the factors are
+orthonormal to about that level and A is reproduced to a few units of it:
+FP32 is held to 2e-5 (relative Frobenius, and ||U^H * U - I||_F / sqrt(m)),
+the singular values to 2e-5 of the largest; FP64 to 1e-12.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import tsvd as ots
+from paper_2212_14318_amd import _native as nat
+from paper_2212_14318_amd import ops
+
+from gpu_util import device, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 2e-5, "fp64": 1e-12}
+
+
+def _run(A64, prec):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    _, p, m, n = A64.shape
+    print(f"qt_tsvd {prec} m={m} n={n} p={p}", flush=True)
+    U, S, V, sig = ops.tsvd(to_dev(A64, dt), precision=prec)
+    torch.cuda.synchronize()
+    return to_np(U), to_np(S), to_np(V), sig.double().cpu().numpy()
+
+
+def _check(A64, prec, U, S, V, sig):
+    tol = TOL[prec]
+    _, p, m, n = A64.shape
+    k = min(m, n)
+    ref_U, ref_S, ref_V, ref_sig = ots.tsvd(A64)
+    smax = max(float(ref_sig.max()), 1e-300)
+    # unique parts
+    assert np.abs(sig - ref_sig).max() <= tol * smax, f"sigma off by {np.abs(sig - ref_sig).max() / smax:.2e}"
+    assert np.sqrt(oracle.qnorm2(S - ref_S)) <= tol * max(np.sqrt(oracle.qnorm2(ref_S)), 1e-300)
+    off = S.copy()
+    d = np.arange(k)
+    off[:2][:, :, d, d] = 0
+    assert np.abs(off).max() <= tol * smax, "S is not f-diagonal"
+    # factors
+    nA = np.sqrt(oracle.qnorm2(A64))
+    R = oracle.tprod(oracle.tprod(U, S), oracle.tconjT(V))
+    rec = np.sqrt(oracle.qnorm2(R - A64)) / max(nA, 1e-300)
+    assert rec <= tol, f"reconstruction {rec:.2e}"
+    for X, name in ((U, "U"), (V, "V")):
+        r = X.shape[2]
+        for G in (oracle.tprod(oracle.tconjT(X), X), oracle.tprod(X, oracle.tconjT(X))):
+            e = np.sqrt(oracle.qnorm2(G - oracle.identity(r, p))) / np.sqrt(r)
+            assert e <= tol, f"{name} not unitary: {e:.2e}"
+    print(f"  sigma {np.abs(sig - ref_sig).max() / smax:.2e}  reconstruction {rec:.2e}", flush=True)
+
+
+# ragged both ways, square, thin, p = 1, 2, odd, even, and Bluestein lengths
+SHAPES = [(12, 7, 5), (7, 12, 6), (16, 16, 1), (9, 5, 2), (5, 9, 3), (1, 1, 4), (1, 6, 3), (6, 1, 7),
+          (33, 20, 8), (20, 33, 11), (40, 40, 9), (64, 17, 13)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("m,n,p", SHAPES)
+def test_tsvd_against_oracle(prec, m, n, p):
+    A64 = synth.quat_tensor(m, n, p, seed=8000 + 97 * m + 13 * n + p)
+    _check(A64, prec, *_run(A64, prec))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_tsvd_rank_deficient_and_zero(prec):
+    X = synth.quat_tensor(14, 3, 6, seed=8100)
+    Y = synth.quat_tensor(3, 10, 6, seed=8101)
+    A64 = oracle.tprod(X, Y)            # chi_f(A) has rank <= 6 < 20
+    U, S, V, sig = _run(A64, prec)
+    _check(A64, prec, U, S, V, sig)
+    assert np.all(sig[:, 3:] <= 10 * TOL[prec] * sig.max())
+    Z = np.zeros((4, 5, 6, 4))
+    U, S, V, sig = _run(Z, prec)
+    assert np.all(sig == 0) and np.all(S == 0)
+    for X in (U, V):
+        r = X.shape[2]
+        e = np.sqrt(oracle.qnorm2(oracle.tprod(oracle.tconjT(X), X) - oracle.identity(r, 5))) / np.sqrt(r)
+        assert e <= TOL[prec]
+
+
+def test_tsvd_real_and_complex_inputs():
+    """Real input: the Fourier singular values are those of numpy's FFT faces
+    (the real t-SVD); complex input: f and -f share those of both faces."""
+    p, m, n = 6, 10, 7
+    A = np.zeros((4, p, m, n))
+    A[0] = synth.quat_tensor(m, n, p, seed=8200)[0]
+    U, S, V, sig = _run(A, "fp32")
+    want = np.linalg.svd(np.fft.fft(A[0], axis=0), compute_uv=False)
+    np.testing.assert_allclose(sig, want, atol=2e-5 * want.max())
+    _check(A, "fp32", U, S, V, sig)
+    A = np.zeros((4, p, m, n))
+    A[:2] = synth.quat_tensor(m, n, p, seed=8201)[:2]
+    _check(A, "fp32", *_run(A, "fp32"))
+
+
+def test_tsvd_scaled_inputs():
+    """Tiny and huge magnitudes: each pair's matrix is scaled by a power of
+    two before the Jacobi sweeps."""
+    base = synth.quat_tensor(9, 6, 5, seed=8300)
+    for sc in (1e-30, 1e25):
+        A64 = base * sc
+        U, S, V, sig = _run(A64, "fp32")
+        _check(A64, "fp32", U, S, V, sig)
+
+
+def test_tsvd_sizes_and_truncation():
+    """256 x 192 x 16 (ragged, complex and quaternion pairs at full tile
+    sizes): sigma against the oracle, reconstruction and the truncation error
+    of the first r diagonal tubes, which must be (1/p) times the sum of the
+    squared dropped Fourier singular values."""
+    m, n, p = 256, 192, 16
+    A64 = synth.quat_tensor(m, n, p, seed=8400)
+    U, S, V, sig = _run(A64, "fp32")
+    ref_sig = ots.tsvd(A64)[3]
+    assert np.abs(sig - ref_sig).max() <= 2e-5 * ref_sig.max()
+    nA2 = oracle.qnorm2(A64)
+    for r in (n, 40):
+        Sr = S.copy()
+        Sr[:, :, r:, :] = 0
+        Ar = oracle.tprod_faces(oracle.tprod_faces(U, Sr), oracle.tconjT(V))
+        err2 = oracle.qnorm2(A64 - Ar)
+        want = float(np.sum(ref_sig[:, r:] ** 2)) / p
+        assert abs(err2 - want) <= 1e-4 * nA2, (r, err2, want)
+
+
+def test_tsvd_argument_errors():
+    dev = device()
+    A = torch.zeros((4, 3, 5, 4), device=dev)
+    U = torch.empty((4, 3, 5, 5), device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    # split precisions are not served
+    st = nat.qt_tsvd(5, 4, 3, A.data_ptr(), U.data_ptr(), None, None, None, nat.QT_SPLIT_BF16, None, 0, stream)
+    assert st == nat.QT_ERR_UNSUPPORTED
+    # output overlapping the input
+    st = nat.qt_tsvd(5, 4, 3, A.data_ptr(), A.data_ptr(), None, None, None, nat.QT_FP32, None, 0, stream)
+    assert st == nat.QT_ERR_INVALID_ARG
+    # beyond the size limits
+    assert nat.qt_tsvd_workspace_size(600, 600, 3, nat.QT_FP32) == 0
+    with pytest.raises(nat.QtError):
+        ops.tsvd(torch.zeros((4, 2, 1100, 3), device=dev))
