@@ -45,6 +45,8 @@ WORKLOADS = {
                           "Hermitian half spectrum, 17 complex products"),
     "chain": dict(cfg=3, desc="chain (A * B) * C, A, B, C 1024x1024x32 quaternion, N(0,1) "
                               "(seeds 3000/3001/3002), kept in the Fourier domain between the products"),
+    "tsvd": dict(cfg=2, desc="quaternion t-SVD A = U * S * V^H of A 256x256x64, components U[0,1) "
+                             "(seed 2000, the colour-video-like tensor)"),
 }
 
 
@@ -120,6 +122,8 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--backward", action="store_true",
                     help="c5: time forward + hand-written backward instead of the forward alone")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: skip the short batch / backward / t-SVD runs")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     return ap.parse_args()
@@ -150,9 +154,11 @@ def main():
     wl = WORKLOADS[args.workload]
     cfg = wl["cfg"]
     if args.workload == "c4":
-        return bench_batched(args, wl, dev, stream)
+        return _emit(bench_batched(args, wl, dev, stream))
     if args.workload == "c5" and args.backward:
-        return bench_backward(args, wl, dev, stream)
+        return _emit(bench_backward(args, wl, dev, stream))
+    if args.workload == "tsvd":
+        return _emit(bench_tsvd(args, wl, dev, stream))
     if args.workload == "chain":
         return bench_chain(args, wl, dev, stream)
     if args.workload == "matvec":
@@ -370,7 +376,41 @@ def main():
     }
     if "fp32" in results and head != "fp32":
         out["speedup_vs_fp32"] = round(results["fp32"]["ms_per_step"] / r["ms_per_step"], 3)
+    if "fp32" in results and "gemm_tflops" in results["fp32"]:
+        # the FP32 tiles form each complex product with three real products, so
+        # the MFMA pipe issues 24 m n s p flops for the 32 m n s p counted
+        r32 = results["fp32"]["gemm_tflops"]
+        out["fp32_roofline"] = {"bound": "mfma", "achieved": round(r32, 3), "peak": PEAK_TFLOPS["fp32"],
+                                "unit": "TFLOP/s", "frac": round(r32 / PEAK_TFLOPS["fp32"], 4),
+                                "issued_frac": round(0.75 * r32 / PEAK_TFLOPS["fp32"], 4),
+                                "issued_flops_per_launch": 24.0 * m * n * s * p,
+                                "note": "frac counts 32 m n s p algorithmic flops; three real products per "
+                                        "complex product issue 0.75 of that on the MFMA pipe"}
+    if not args.no_extras:
+        out["extra_workloads"] = extra_workloads(args, dev, stream)
     print(json.dumps(out), flush=True)
+
+
+def extra_workloads(args, dev, stream):
+    """Shorter runs of the batch, differentiation and t-SVD workloads, so that
+    one bench line carries their times too."""
+    import copy
+    sub = copy.copy(args)
+    sub.steps, sub.warmup = 20, 5
+    extras = {}
+    for name, fn in (("c4", bench_batched), ("c5_fwd_bwd", bench_backward), ("tsvd", bench_tsvd)):
+        wl = WORKLOADS["c5" if name == "c5_fwd_bwd" else name]
+        sub.precisions = "fp32" if name == "tsvd" else args.precisions
+        sub.no_cpu_baseline = True
+        try:
+            res = fn(sub, wl, dev, stream)
+        except Exception as e:      # report, never hide the headline
+            log(f"[bench] extra workload {name} failed: {e}")
+            extras[name] = {"error": str(e)}
+            continue
+        extras[name] = {"workload": res["config"]["workload"], "steps": sub.steps,
+                        "per_precision": res["per_precision"], "roofline": res.get("roofline")}
+    return extras
 
 
 def _emit(out):
@@ -413,13 +453,13 @@ def bench_batched(args, wl, dev, stream):
         plan.close()
         log(f"[bench] c4 {prec}: {ms:.3f} ms per replay, {res[prec]['tflops_equiv']:.1f} TFLOP/s-equiv")
     head = precs[0]
-    _emit({"metric": "T-product TFLOP/s-equiv & % roofline, split-BF16 vs FP32 at stated rel. error",
-           "value": round(res[head]["tflops_equiv"], 3), "unit": "TFLOP/s-equiv", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res[head]["ms_per_step"], 4),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "bf16x3-split/f32-acc" if head == "split_bf16" else "f32", "data": "synthetic",
-           "config": {"workload": wl["desc"], "precision": head, "flops_per_step": F},
-           "per_precision": res, "roofline": None, "cpu_baseline": None})
+    return {"metric": "T-product TFLOP/s-equiv & % roofline, split-BF16 vs FP32 at stated rel. error",
+            "value": round(res[head]["tflops_equiv"], 3), "unit": "TFLOP/s-equiv", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res[head]["ms_per_step"], 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16x3-split/f32-acc" if head == "split_bf16" else "f32", "data": "synthetic",
+            "config": {"workload": wl["desc"], "precision": head, "flops_per_step": F},
+            "per_precision": res, "roofline": None, "cpu_baseline": None}
 
 
 def bench_backward(args, wl, dev, stream):
@@ -456,13 +496,131 @@ def bench_backward(args, wl, dev, stream):
         res[prec] = {"ms_per_step": ms, "tflops_equiv": F / (ms * 1e-3) / 1e12}
         log(f"[bench] c5 fwd+bwd {prec}: {ms:.3f} ms/step, {res[prec]['tflops_equiv']:.1f} TFLOP/s-equiv")
     head = precs[0]
-    _emit({"metric": "T-product TFLOP/s-equiv & % roofline, split-BF16 vs FP32 at stated rel. error",
-           "value": round(res[head]["tflops_equiv"], 3), "unit": "TFLOP/s-equiv", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res[head]["ms_per_step"], 4),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "bf16x3-split/f32-acc" if head == "split_bf16" else "f32", "data": "synthetic",
-           "config": {"workload": wl["desc"] + " + backward", "precision": head, "flops_per_step": F},
-           "per_precision": res, "roofline": None, "cpu_baseline": None})
+    return {"metric": "T-product TFLOP/s-equiv & % roofline, split-BF16 vs FP32 at stated rel. error",
+            "value": round(res[head]["tflops_equiv"], 3), "unit": "TFLOP/s-equiv", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res[head]["ms_per_step"], 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16x3-split/f32-acc" if head == "split_bf16" else "f32", "data": "synthetic",
+            "config": {"workload": wl["desc"] + " + backward", "precision": head, "flops_per_step": F},
+            "per_precision": res, "roofline": None, "cpu_baseline": None}
+
+
+def svd_flops(rows, cols):
+    """Operation count of a complex SVD with both singular-vector sets, rows
+    >= cols: the real count 4 r^2 c + 8 r c^2 + 9 c^3 (Golub and Van Loan's
+    R-SVD) times 4 real operations per complex one."""
+    return 4.0 * (4.0 * rows * rows * cols + 8.0 * rows * cols * cols + 9.0 * cols ** 3)
+
+
+def tsvd_flops(m, n, p):
+    """Algorithmic work of the t-SVD's pair kernel: one complex SVD of the
+    2 max(m,n) x 2 min(m,n) matrix chi_f(A) per pair {f, -f} with f != -f, and
+    half of that for each self-paired frequency (a quaternion SVD of half the
+    size: an eighth of the elements at four times the operations each)."""
+    r, c = max(m, n), min(m, n)
+    selfp = 1 if p % 2 else 2
+    pairs = p // 2 + 1 - selfp
+    return (pairs + 0.5 * selfp) * svd_flops(2 * r, 2 * c)
+
+
+def bench_tsvd(args, wl, dev, stream):
+    """t-SVD workload: one step = qt_tsvd (tube FFT, pair kernel, S^ fill,
+    inverse FFTs of U^, V^, S^).  The pair kernel is timed on its own through
+    qt_fourier_tsvd on the transformed input; its roofline is the FP32 vector
+    ALU (the Jacobi sweeps are column updates in VALU with the columns held in
+    L2), reported against the SVD operation count."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from oracle import tsvd as ots
+    from paper_2212_14318_amd import _native as nat
+
+    A64 = synth.config_inputs(2)[0]
+    _, p, m, n = A64.shape
+    F = tsvd_flops(m, n, p)
+    res = {}
+    precs = [x for x in args.precisions.split(",") if x]
+    if precs and precs[0].startswith("split"):
+        precs = ["fp32"]
+    sh = stream.cuda_stream
+    ref_sig = None
+    for prec in precs:
+        P = nat.PRECISIONS[prec]
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        A = torch.from_numpy(A64).to(dev, dt)
+        k = min(m, n)
+        U = torch.empty((4, p, m, m), dtype=dt, device=dev)
+        S = torch.empty((4, p, m, n), dtype=dt, device=dev)
+        V = torch.empty((4, p, n, n), dtype=dt, device=dev)
+        sig = torch.empty((p, k), dtype=dt, device=dev)
+        need = nat.qt_tsvd_workspace_size(m, n, p, P)
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        lda, ldu = nat.qt_fourier_ld(n), nat.qt_fourier_ld(m)
+        Ah = torch.empty((4, p, m, lda), dtype=dt, device=dev)
+        Uh = torch.empty((4, p, m, ldu), dtype=dt, device=dev)
+        Vh = torch.empty((4, p, n, lda), dtype=dt, device=dev)
+        sig2 = torch.empty_like(sig)
+        pneed = nat.qt_fourier_tsvd_workspace_size(m, n, p, P)
+        pws = torch.empty(pneed, dtype=torch.uint8, device=dev)
+
+        def whole():
+            nat.check(nat.qt_tsvd(m, n, p, A.data_ptr(), U.data_ptr(), S.data_ptr(), V.data_ptr(), sig.data_ptr(),
+                                  P, ws.data_ptr(), need, sh), "qt_tsvd")
+
+        def pairs():
+            nat.check(nat.qt_fourier_tsvd(m, n, p, Ah.data_ptr(), lda, Uh.data_ptr(), ldu, Vh.data_ptr(), lda,
+                                          sig2.data_ptr(), P, pws.data_ptr(), pneed, sh), "qt_fourier_tsvd")
+
+        nat.check(nat.qt_tube_fft(m, n, p, A.data_ptr(), n, Ah.data_ptr(), lda, 0, P, sh), "qt_tube_fft")
+        steps, warm = max(1, min(args.steps, 10)), max(1, min(args.warmup, 2))
+        times = {}
+        for name, fn in (("whole", whole), ("pairs", pairs)):
+            for _ in range(warm):
+                fn()
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record(stream)
+            for _ in range(steps):
+                fn()
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            times[name] = ev[0].elapsed_time(ev[1]) / steps
+        if ref_sig is None:
+            ref_sig = ots.tsvd(A64)[3]
+        got = sig.double().cpu().numpy()
+        err = float(np.abs(got - ref_sig).max() / ref_sig.max())
+        same = bool(torch.equal(sig, sig2))
+        res[prec] = {"ms_per_step": times["whole"], "pair_kernel_ms": times["pairs"],
+                     "pair_kernel_tflops": F / (times["pairs"] * 1e-3) / 1e12,
+                     "sigma_max_rel_err": err, "stage_equals_qt_tsvd": same, "steps": steps}
+        log(f"[bench] tsvd {prec}: {times['whole']:.3f} ms per qt_tsvd, pair kernel {times['pairs']:.3f} ms "
+            f"({res[prec]['pair_kernel_tflops']:.3f} TFLOP/s of SVD work), sigma err {err:.2e}")
+    head = precs[0]
+    r = res[head]
+    cpu = None
+    if not getattr(args, "no_cpu_baseline", False):
+        import threadpoolctl
+        threads = max([d.get("num_threads", 1) for d in threadpoolctl.threadpool_info()] or [1])
+        t0 = time.perf_counter()
+        ots.tsvd(A64)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": F / t_cpu / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+               "cpu_model": cpu_model(),
+               "sample": f"the whole workload by the oracle's t-SVD (numpy complex128 SVD per frequency pair), "
+                         f"{t_cpu:.1f} s"}
+    peak = PEAK_TFLOPS["fp32"] if head == "fp32" else PEAK_TFLOPS["fp64"]
+    return {"metric": "T-product TFLOP/s-equiv & % roofline, split-BF16 vs FP32 at stated rel. error",
+            "value": round(F / (r["ms_per_step"] * 1e-3) / 1e12, 4), "unit": "TFLOP/s", "n_gpus": 1,
+            "steps": r["steps"], "warmup": 2, "ms_per_step": round(r["ms_per_step"], 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32" if head == "fp32" else "f64", "data": "synthetic",
+            "config": {"workload": wl["desc"], "precision": head, "svd_flops_per_step": F},
+            "roofline": {"bound": "alu", "achieved": round(r["pair_kernel_tflops"], 4), "peak": peak,
+                         "unit": "TFLOP/s", "frac": round(r["pair_kernel_tflops"] / peak, 5), "traffic": None,
+                         "kernel": "tsvd_pair_kernel (qt_fourier_tsvd)"},
+            "per_precision": res, "cpu_baseline": cpu}
 
 
 def bench_chain(args, wl, dev, stream):

@@ -339,6 +339,21 @@ size_t qt_tsvd_workspace_size(int m, int n, int p, qt_precision precision);
 qt_status qt_tsvd(int m, int n, int p, const void* A, void* U, void* S, void* V, void* sigma,
                   qt_precision precision, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Workspace bytes of qt_fourier_tsvd (0 if invalid or beyond the limits). */
+size_t qt_fourier_tsvd_workspace_size(int m, int n, int p, qt_precision precision);
+
+/* The middle step of qt_tsvd alone, for tensors kept in the Fourier domain:
+ * from Ah = the tube FFT of A ([4][p][m][lda], as written by qt_tube_fft in
+ * QT_FP32 / QT_FP64) it writes Uh = the tube FFT of U ([4][p][m][ldu]),
+ * Vh = that of V ([4][p][n][ldv]) and sigma (p x min(m, n)); S^ is the
+ * f-diagonal tensor with S1^[f](i, i) = sigma[f][i] and no other non-zero
+ * entry.  Columns beyond m (Uh) and n (Vh) are not written.  ws: device
+ * scratch of at least qt_fourier_tsvd_workspace_size() bytes (required, no
+ * NULL form).  Same precisions, limits and error behaviour as qt_tsvd; no
+ * buffer may overlap another. */
+qt_status qt_fourier_tsvd(int m, int n, int p, const void* Ah, int lda, void* Uh, int ldu, void* Vh, int ldv,
+                          void* sigma, qt_precision precision, void* ws, size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -64,6 +64,8 @@ SIGNATURES = {
     "qt_tprod_backward": (_I, [_I, _I, _I, _I, _P, _P, _P, _P, _P, _I, _P, _SZ, _P]),
     "qt_tsvd_workspace_size": (_SZ, [_I, _I, _I, _I]),
     "qt_tsvd": (_I, [_I, _I, _I, _P, _P, _P, _P, _P, _I, _P, _SZ, _P]),
+    "qt_fourier_tsvd_workspace_size": (_SZ, [_I, _I, _I, _I]),
+    "qt_fourier_tsvd": (_I, [_I, _I, _I, _P, _I, _P, _I, _P, _I, _P, _I, _P, _SZ, _P]),
 }
 
 _lib = None
@@ -204,3 +206,11 @@ def qt_tsvd_workspace_size(m, n, p, precision) -> int:
 
 def qt_tsvd(m, n, p, A, U, S, V, sigma, precision, ws, ws_bytes, stream=0) -> int:
     return lib().qt_tsvd(m, n, p, A, U, S, V, sigma, precision, ws, ws_bytes, stream)
+
+
+def qt_fourier_tsvd_workspace_size(m, n, p, precision) -> int:
+    return lib().qt_fourier_tsvd_workspace_size(m, n, p, precision)
+
+
+def qt_fourier_tsvd(m, n, p, Ah, lda, Uh, ldu, Vh, ldv, sigma, precision, ws, ws_bytes, stream=0) -> int:
+    return lib().qt_fourier_tsvd(m, n, p, Ah, lda, Uh, ldu, Vh, ldv, sigma, precision, ws, ws_bytes, stream)

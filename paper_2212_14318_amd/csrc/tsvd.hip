@@ -163,6 +163,97 @@ __device__ bool jacobi_pair(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool quat
     return true;
 }
 
+// The same step with both columns held in registers between the inner
+// products and the update (K loads per lane and column half issued together):
+// for h, hq <= 64 K.
+template <typename T, typename V, int K>
+__device__ bool jacobi_pair_reg(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool quat, T tol, Acc negl2, int lane) {
+    V a0[K], a1[K], b0[K], b1[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        const int k = lane + 64 * t;
+        const bool in = k < h;
+        a0[t] = in ? xi[k] : V{0, 0};
+        a1[t] = in ? xi[k + h] : V{0, 0};
+        b0[t] = in ? xj[k] : V{0, 0};
+        b1[t] = in ? xj[k + h] : V{0, 0};
+    }
+    Acc al = 0, be = 0, g1r = 0, g1i = 0, g2r = 0, g2i = 0;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        const Acc a0x = a0[t].x, a0y = a0[t].y, a1x = a1[t].x, a1y = a1[t].y;
+        const Acc b0x = b0[t].x, b0y = b0[t].y, b1x = b1[t].x, b1y = b1[t].y;
+        al += a0x * a0x + a0y * a0y + a1x * a1x + a1y * a1y;
+        be += b0x * b0x + b0y * b0y + b1x * b1x + b1y * b1y;
+        g1r += a0x * b0x + a0y * b0y + a1x * b1x + a1y * b1y;
+        g1i += a0x * b0y - a0y * b0x + a1x * b1y - a1y * b1x;
+        if (quat) {
+            g2r += -(a0x * b1x - a0y * b1y) + (a1x * b0x - a1y * b0y);
+            g2i += (a0x * b1y + a0y * b1x) - (a1x * b0y + a1y * b0x);
+        }
+    }
+    al = wave_sum(al);
+    be = wave_sum(be);
+    g1r = wave_sum(g1r);
+    g1i = wave_sum(g1i);
+    if (quat) {
+        g2r = wave_sum(g2r);
+        g2i = wave_sum(g2i);
+    }
+    if (al <= negl2 || be <= negl2) return false;
+    const Acc gn = sqrt(g1r * g1r + g1i * g1i + g2r * g2r + g2i * g2i);
+    if (!(gn > (Acc)tol * sqrt(al * be))) return false;
+    const V e1c = V{T(g1r / gn), T(-g1i / gn)}, e2c = V{T(g2r / gn), T(-g2i / gn)};
+    const Acc zeta = (be - al) / (2 * gn);
+    const Acc tt = (zeta >= 0 ? Acc(1) : Acc(-1)) / (fabs(zeta) + sqrt(Acc(1) + zeta * zeta));
+    const Acc csd = Acc(1) / sqrt(Acc(1) + tt * tt);
+    const T cs = T(csd), sn = T(csd * tt);
+    auto rot = [&](V& u0, V& u1, V& w0, V& w1) {
+        V c0 = cmul(e1c, w0), c1 = cmul(e1c, w1);
+        if (quat) {
+            c0 = cadd(c0, cmul(e2c, cneg(cconj(w1))));
+            c1 = cadd(c1, cmul(e2c, cconj(w0)));
+        }
+        const V n0 = csub(cscale(u0, cs), cscale(c0, sn)), n1 = csub(cscale(u1, cs), cscale(c1, sn));
+        w0 = cadd(cscale(u0, sn), cscale(c0, cs));
+        w1 = cadd(cscale(u1, sn), cscale(c1, cs));
+        u0 = n0;
+        u1 = n1;
+    };
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        const int k = lane + 64 * t;
+        if (k < h) {
+            rot(a0[t], a1[t], b0[t], b1[t]);
+            xi[k] = a0[t];
+            xi[k + h] = a1[t];
+            xj[k] = b0[t];
+            xj[k + h] = b1[t];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        const int k = lane + 64 * t;
+        const bool in = k < hq;
+        a0[t] = in ? qi[k] : V{0, 0};
+        a1[t] = in ? qi[k + hq] : V{0, 0};
+        b0[t] = in ? qj[k] : V{0, 0};
+        b1[t] = in ? qj[k + hq] : V{0, 0};
+    }
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        const int k = lane + 64 * t;
+        if (k < hq) {
+            rot(a0[t], a1[t], b0[t], b1[t]);
+            qi[k] = a0[t];
+            qi[k + hq] = a1[t];
+            qj[k] = b0[t];
+            qj[k + hq] = b1[t];
+        }
+    }
+    return true;
+}
+
 // Write column vector u (2*half entries, the slot-th column of chi_f(Y) for an
 // half x half quaternion tensor Y) into Y^ at frequencies f and g = -f:
 //   slot j <  half: Y^1[f](:, j) = top,        Y^2[g](:, j) = -conj(bottom)
@@ -275,10 +366,13 @@ __global__ void __launch_bounds__(kThreads) tsvd_pair_kernel(TsvdArgs<T> a) {
             for (int q = wave; q < nup / 2; q += kWaves) {
                 const int i = circle(q, t, nup), j = circle(nup - 1 - q, t, nup);
                 if (i >= nu || j >= nu) continue;
-                if (jacobi_pair<T, V>(X + (size_t)i * R, X + (size_t)j * R, Q + (size_t)i * Rq,
-                                      Q + (size_t)j * Rq, r, c, quat, tol, negl2, lane) &&
-                    lane == 0)
-                    s_flag = 1;
+                V *xi = X + (size_t)i * R, *xj = X + (size_t)j * R;
+                V *qi = Q + (size_t)i * Rq, *qj = Q + (size_t)j * Rq;
+                const bool rotated =
+                    (r <= 64 && c <= 64)     ? jacobi_pair_reg<T, V, 1>(xi, xj, qi, qj, r, c, quat, tol, negl2, lane)
+                    : (r <= 256 && c <= 256) ? jacobi_pair_reg<T, V, 4>(xi, xj, qi, qj, r, c, quat, tol, negl2, lane)
+                                             : jacobi_pair<T, V>(xi, xj, qi, qj, r, c, quat, tol, negl2, lane);
+                if (rotated && lane == 0) s_flag = 1;
             }
             __syncthreads();
         }
@@ -450,6 +544,16 @@ bool tsvd_dims_ok(int m, int n, int p) {
            (m > n ? m : n) <= kMaxMax;
 }
 
+// The pair kernel on a transformed A^: U^, V^ and sigma.
+template <typename T>
+hipError_t launch_tsvd_pairs(int m, int n, int p, const T* Ah, int lda, T* Uh, int ldu, T* Vh, int ldv, T* sigma,
+                             char* pairs, hipStream_t stream) {
+    const size_t pb = pair_scratch_bytes<T>(m, n);
+    TsvdArgs<T> args{Ah, Uh, Vh, sigma, pairs, pb, m, n, p, lda, ldu, ldv};
+    hipLaunchKernelGGL(tsvd_pair_kernel<T>, dim3(p / 2 + 1), dim3(kThreads), 0, stream, args);
+    return hipGetLastError();
+}
+
 template <typename T>
 int run_tsvd(int m, int n, int p, const T* A, T* U, T* S, T* V, T* sigma_out, int prec, char* ws,
              hipStream_t stream) {
@@ -466,9 +570,8 @@ int run_tsvd(int m, int n, int p, const T* A, T* U, T* S, T* V, T* sigma_out, in
 
     FftJob<T> fwd[1] = {{A, Ah, m, n, n, lda, 0}};
     if (launch_tube_fft<T>(p, false, fwd, 1, tw, stream) != hipSuccess) return QT_ERR_HIP;
-    TsvdArgs<T> args{Ah, Uh, Vh, sig, ws + L.pairs, L.pair_bytes, m, n, p, lda, ldu, ldv};
-    hipLaunchKernelGGL(tsvd_pair_kernel<T>, dim3(p / 2 + 1), dim3(kThreads), 0, stream, args);
-    if (hipGetLastError() != hipSuccess) return QT_ERR_HIP;
+    if (launch_tsvd_pairs<T>(m, n, p, Ah, lda, Uh, ldu, Vh, ldv, sig, ws + L.pairs, stream) != hipSuccess)
+        return QT_ERR_HIP;
     if (S) {
         const long total = 4L * p * m * lda;
         const int blocks = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
@@ -527,6 +630,44 @@ extern "C" {
 size_t qt_tsvd_workspace_size(int m, int n, int p, qt_precision precision) {
     if ((precision != QT_FP32 && precision != QT_FP64) || !qt::tsvd_dims_ok(m, n, p)) return 0;
     return qt::tsvd_layout(m, n, p, precision).total;
+}
+
+size_t qt_fourier_tsvd_workspace_size(int m, int n, int p, qt_precision precision) {
+    if ((precision != QT_FP32 && precision != QT_FP64) || !qt::tsvd_dims_ok(m, n, p)) return 0;
+    const size_t pb = precision == QT_FP64 ? qt::pair_scratch_bytes<double>(m, n)
+                                           : qt::pair_scratch_bytes<float>(m, n);
+    return (size_t)(p / 2 + 1) * pb;
+}
+
+qt_status qt_fourier_tsvd(int m, int n, int p, const void* Ah, int lda, void* Uh, int ldu, void* Vh, int ldv,
+                          void* sigma, qt_precision precision, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (precision != QT_FP32 && precision != QT_FP64 && precision != QT_SPLIT_BF16 && precision != QT_SPLIT_FP16)
+        return QT_ERR_INVALID_ARG;
+    if (m < 1 || n < 1 || p < 1 || !Ah || !Uh || !Vh || !sigma || !ws) return QT_ERR_INVALID_ARG;
+    if (lda < n || ldu < m || ldv < n) return QT_ERR_INVALID_ARG;
+    if (!qt::aligned16(Ah) || !qt::aligned16(Uh) || !qt::aligned16(Vh) || !qt::aligned16(sigma) ||
+        !qt::aligned16(ws))
+        return QT_ERR_INVALID_ARG;
+    if (precision != QT_FP32 && precision != QT_FP64) return QT_ERR_UNSUPPORTED;
+    if (!qt::tsvd_dims_ok(m, n, p)) return QT_ERR_UNSUPPORTED;
+    const size_t es = precision == QT_FP64 ? 8 : 4;
+    const size_t need = qt_fourier_tsvd_workspace_size(m, n, p, precision);
+    if (ws_bytes < need) return QT_ERR_INVALID_ARG;
+    const size_t k = m < n ? m : n;
+    const void* bufs[5] = {Ah, Uh, Vh, sigma, ws};
+    const size_t sz[5] = {4 * (size_t)p * m * lda * es, 4 * (size_t)p * m * ldu * es, 4 * (size_t)p * n * ldv * es,
+                          (size_t)p * k * es, need};
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < a; ++b)
+            if (qt::overlaps(bufs[a], sz[a], bufs[b], sz[b])) return QT_ERR_INVALID_ARG;
+    hipError_t e;
+    if (precision == QT_FP64)
+        e = qt::launch_tsvd_pairs<double>(m, n, p, (const double*)Ah, lda, (double*)Uh, ldu, (double*)Vh, ldv,
+                                          (double*)sigma, (char*)ws, stream);
+    else
+        e = qt::launch_tsvd_pairs<float>(m, n, p, (const float*)Ah, lda, (float*)Uh, ldu, (float*)Vh, ldv,
+                                         (float*)sigma, (char*)ws, stream);
+    return e == hipSuccess ? QT_OK : QT_ERR_HIP;
 }
 
 qt_status qt_tsvd(int m, int n, int p, const void* A, void* U, void* S, void* V, void* sigma,

@@ -38,3 +38,12 @@ def test_traffic_only_for_matching_fingerprint():
     assert (t is not None) == (fp in recorded)
     assert bench.measured_traffic("c2", "split_bf16") is None
     assert bench.measured_traffic("c3", "fp32") is None
+
+
+def test_tsvd_flop_model():
+    # one complex SVD of the 2r x 2c matrix per pair, half for each self-paired frequency
+    one = bench.svd_flops(2 * 256, 2 * 192)
+    assert one == 4.0 * (4 * 512 ** 2 * 384 + 8 * 512 * 384 ** 2 + 9 * 384 ** 3)
+    assert bench.tsvd_flops(256, 192, 1) == pytest.approx(0.5 * one)
+    assert bench.tsvd_flops(192, 256, 16) == pytest.approx((7 + 1.0) * one)     # pairs 1..7, f = 0 and 8
+    assert bench.tsvd_flops(256, 192, 15) == pytest.approx((7 + 0.5) * one)

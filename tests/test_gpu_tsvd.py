@@ -152,3 +152,36 @@ def test_tsvd_argument_errors():
     assert nat.qt_tsvd_workspace_size(600, 600, 3, nat.QT_FP32) == 0
     with pytest.raises(nat.QtError):
         ops.tsvd(torch.zeros((4, 2, 1100, 3), device=dev))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_fourier_tsvd_stage_matches_qt_tsvd(prec):
+    """qt_tube_fft + qt_fourier_tsvd + inverse transforms give bit for bit the
+    U, V and sigma of qt_tsvd (same kernels on the same A^)."""
+    dev = device()
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    m, n, p = 21, 34, 7
+    A64 = synth.quat_tensor(m, n, p, seed=8500)
+    A = to_dev(A64, dt)
+    U0, S0, V0, sig0 = ops.tsvd(A, precision=prec)
+    P = nat.PRECISIONS[prec]
+    lda, ldu, ldv = nat.qt_fourier_ld(n), nat.qt_fourier_ld(m), nat.qt_fourier_ld(n)
+    Ah = torch.full((4, p, m, lda), float("nan"), dtype=dt, device=dev)
+    Uh = torch.full((4, p, m, ldu), float("nan"), dtype=dt, device=dev)
+    Vh = torch.full((4, p, n, ldv), float("nan"), dtype=dt, device=dev)
+    sig = torch.empty((p, min(m, n)), dtype=dt, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    nat.check(nat.qt_tube_fft(m, n, p, A.data_ptr(), n, Ah.data_ptr(), lda, 0, P, stream), "fft")
+    need = nat.qt_fourier_tsvd_workspace_size(m, n, p, P)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    st = nat.qt_fourier_tsvd(m, n, p, Ah.data_ptr(), lda, Uh.data_ptr(), ldu, Vh.data_ptr(), ldv, sig.data_ptr(),
+                             P, ws.data_ptr(), need, stream)
+    assert st == nat.QT_OK
+    U = torch.empty((4, p, m, m), dtype=dt, device=dev)
+    V = torch.empty((4, p, n, n), dtype=dt, device=dev)
+    nat.check(nat.qt_tube_fft(m, m, p, Uh.data_ptr(), ldu, U.data_ptr(), m, 1, P, stream), "ifft U")
+    nat.check(nat.qt_tube_fft(n, n, p, Vh.data_ptr(), ldv, V.data_ptr(), n, 1, P, stream), "ifft V")
+    torch.cuda.synchronize()
+    assert torch.equal(sig, sig0) and torch.equal(U, U0) and torch.equal(V, V0)
+    assert nat.qt_fourier_tsvd(m, n, p, Ah.data_ptr(), lda, Uh.data_ptr(), ldu, Vh.data_ptr(), ldv, sig.data_ptr(),
+                               P, ws.data_ptr(), need - 1, stream) == nat.QT_ERR_INVALID_ARG
