@@ -122,6 +122,9 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--backward", action="store_true",
                     help="c5: time forward + hand-written backward instead of the forward alone")
+    ap.add_argument("--p", type=int, default=0,
+                    help="c2 / c3: draw the inputs with this many faces instead (same shapes, seeds and "
+                         "distribution), e.g. a prime p for the Bluestein transforms")
     ap.add_argument("--no-extras", action="store_true",
                     help="default workload only: skip the short batch / backward / t-SVD runs")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -166,8 +169,18 @@ def main():
     if args.workload in ("complex", "real"):
         return bench_complex(args, wl, dev, stream, real=args.workload == "real")
     t0 = time.time()
-    inputs = synth.config_inputs(cfg)
-    A64, B64 = inputs[0], inputs[1]
+    if args.p:
+        if cfg not in (2, 3):
+            print("bench.py: --p applies to the c2 and c3 workloads", file=sys.stderr)
+            sys.exit(2)
+        c = synth.CONFIGS[cfg]
+        A64 = synth.quat_tensor(c["m"], c["n"], args.p, 1000 * cfg, c["dist"])
+        B64 = synth.quat_tensor(c["n"], c["s"], args.p, 1000 * cfg + 1, c["dist"])
+        wl = dict(wl, desc=wl["desc"].replace(f"x{c['p']} ", f"x{args.p} ").replace(
+            f"x{c['p']} quaternion", f"x{args.p} quaternion") + f" (p = {args.p})")
+    else:
+        inputs = synth.config_inputs(cfg)
+        A64, B64 = inputs[0], inputs[1]
     _, p, m, n = A64.shape
     s = B64.shape[3]
     log(f"[bench] inputs {args.workload} m={m} n={n} s={s} p={p} drawn in {time.time() - t0:.1f}s")

@@ -74,7 +74,9 @@ typedef enum {
     QT_ERR_UNSUPPORTED = -2,  /* valid request this build cannot serve (e.g. p too large) */
     QT_ERR_ALLOC = -3,        /* device allocation failed (plan cache, or a workspace requested with ws == NULL) */
     QT_ERR_HIP = -4,          /* a HIP runtime call or kernel launch failed */
-    QT_ERR_TOO_LARGE = -5     /* the problem does not fit the fixed scratch of qt_tprod_noalloc */
+    QT_ERR_TOO_LARGE = -5,    /* the problem does not fit the fixed scratch of qt_tprod_noalloc */
+    QT_STATUS_INT_RANGE = 0x7fffffff  /* not a status: gives the enum the full int range, so
+                                         that any int a caller passes is a valid value */
 } qt_status;
 
 typedef enum {
@@ -90,7 +92,9 @@ typedef enum {
                            qt_tprod_batched / qt_batched_plan_create,
                            qt_tprod_complex and qt_tprod_real return
                            QT_ERR_UNSUPPORTED for it */
-    QT_FP64 = 3         /* every step in double (small problems, validation) */
+    QT_FP64 = 3,        /* every step in double (small problems, validation) */
+    QT_PRECISION_INT_RANGE = 0x7fffffff  /* not a precision: full int range (checked values
+                                            outside 0..3 are rejected, not undefined) */
 } qt_precision;
 
 /* Largest p served (QT_ERR_UNSUPPORTED above it).  Every p in [1, QT_MAX_P]

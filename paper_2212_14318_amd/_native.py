@@ -9,7 +9,10 @@ from __future__ import annotations
 import ctypes
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libqtprod.so")
+# QTPROD_LIB selects another build of the same library (the host-sanitized
+# build of the argument-validation tests); default: the in-tree library.
+LIB_PATH = os.environ.get("QTPROD_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                        "libqtprod.so")
 
 QT_OK = 0
 QT_ERR_INVALID_ARG = -1
