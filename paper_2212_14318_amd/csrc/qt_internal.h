@@ -40,10 +40,13 @@ struct FftJob {
 // (k < p); hat_fwd / hat_inv = length-M DFTs of the chirp sequence and of its
 // conjugate; twm = exp(-2 pi i j / M), j < M/2.  All made in FP64 on the
 // device, stored in both precisions.  M = 0 when p does not need them.
+// The spectra are kept in two orders: hat_* in the order that the LDS
+// kernel's decimation-in-frequency passes leave the frequencies in, hatn_* in
+// natural order (register-resident kernels); twf = exp(-2 pi i j / M), j < M.
 struct BluesteinTables {
     int M;
-    double2 *chirp64, *hat_fwd64, *hat_inv64, *twm64;
-    float2 *chirp32, *hat_fwd32, *hat_inv32, *twm32;
+    double2 *chirp64, *hat_fwd64, *hat_inv64, *twm64, *hatn_fwd64, *hatn_inv64, *twf64;
+    float2 *chirp32, *hat_fwd32, *hat_inv32, *twm32, *hatn_fwd32, *hatn_inv32, *twf32;
 };
 
 // Twiddle tables of one p: tw[k] = exp(-2 pi i k / p), k in [0, p), made in
@@ -65,6 +68,11 @@ hipError_t launch_bluestein_tables(int p, const BluesteinTables& bt, hipStream_t
 template <typename T>
 hipError_t launch_bluestein(int p, bool inverse, const FftJob<T>* jobs, int njobs,
                             const BluesteinTables& bt, hipStream_t stream);
+// The register-resident variant (one tube per thread) for convolution lengths
+// M <= 64 (FP32) / 32 (FP64); hipErrorNotSupported for longer ones.
+template <typename T>
+hipError_t launch_bluestein_reg(int p, bool inverse, const FftJob<T>* jobs, int njobs,
+                                const BluesteinTables& bt, hipStream_t stream);
 
 // Forward (inverse = false) or inverse (inverse = true, with the 1/p scale)
 // tube FFT of up to two jobs in one launch.  Returns hipSuccess or the launch
