@@ -102,7 +102,10 @@ typedef enum {
  * 2, 3, 5, 7) up to 128 (64 for QT_FP64) have register-resident tube FFTs,
  * every other p goes through Bluestein's algorithm (chirp tables in FP64 on
  * the device), whose length-M convolution (M the power of two >= 2p - 1) is
- * held in one workgroup's LDS.  The batched path serves 7-smooth p <= 64. */
+ * held in one workgroup's LDS.  The batched path serves every p as well: its
+ * own batched tube-FFT launches cover 7-smooth p <= 64, and problems of any
+ * other length get tube-FFT launches of their own inside the same call or
+ * plan (their products still share the persistent product launches). */
 #define QT_MAX_P 4096
 
 /* Library ABI version (major * 100 + minor). */
@@ -199,7 +202,8 @@ size_t qt_batched_workspace_size(int count, const qt_problem* probs, qt_precisio
  * memory, so the call returns once it is staged.
  * probs is a HOST array read before the call returns.  Each problem obeys the
  * single-call preconditions; outputs must not overlap any input or output.
- * precision: QT_FP32 or QT_SPLIT_BF16; every p must be 7-smooth and <= 64.
+ * precision: QT_FP32 or QT_SPLIT_BF16; any p <= QT_MAX_P (problems whose p
+ * is not 7-smooth or exceeds 64 get tube-FFT launches of their own).
  * The first call per device and precision runs the autotuner (allocates and
  * synchronises once).  Same arithmetic as qt_tprod per problem (tile shapes
  * may differ, hence rounding order).  For graph replays use the plan API. */
@@ -239,7 +243,7 @@ typedef struct qt_batched_plan_s* qt_batched_plan;
  * autotuner if it has not run for this device and precision, create missing
  * twiddle tables, upload the work lists into ws, synchronise `stream`, and
  * capture + instantiate the graph.  Not capture-safe itself.  precision:
- * QT_FP32 or QT_SPLIT_BF16; every p must be 7-smooth and <= 64 (else
+ * QT_FP32 or QT_SPLIT_BF16; any p <= QT_MAX_P (else
  * QT_ERR_UNSUPPORTED). */
 qt_status qt_batched_plan_create(int count, const qt_problem* probs, qt_precision precision, void* ws,
                            size_t ws_bytes, hipStream_t stream, qt_batched_plan* plan);

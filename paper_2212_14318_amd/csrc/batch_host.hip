@@ -308,7 +308,18 @@ struct FftBucket {
     int p, pol, first, count;
 };
 
+// A problem whose tube length has no batched FFT kernel (not 7-smooth, or
+// p > 64): its transforms are launched on their own (register-resident or
+// Bluestein kernels of the single-problem path); its products still go into
+// the shared persistent launches.
+struct SingleFft {
+    int p;
+    Twiddles tw;
+    FftJob<float> fwd[2], inv;
+};
+
 struct HostLists {
+    std::vector<SingleFft> single;
     std::vector<BatchFftJob> fwd_jobs, inv_jobs;
     std::vector<BatchFftItem> fwd_items, inv_items;
     std::vector<FftBucket> fwd_buckets, inv_buckets;
@@ -336,8 +347,15 @@ int build_lists(int count, const qt_problem* probs, int prec, char* ws, const De
         float* Ah = reinterpret_cast<float*>(ws + off); off += fourier_bytes(q.m, q.n, q.p);
         float* Bh = reinterpret_cast<float*>(ws + off); off += fourier_bytes(q.n, q.s, q.p);
         float* Ch = reinterpret_cast<float*>(ws + off); off += fourier_bytes(q.m, q.s, q.p);
-        const int pol = tune.fft_pol[q.p];
+        const int pol = q.p <= 64 ? tune.fft_pol[q.p] : 0;
         const int pack = prec == QT_SPLIT_BF16 ? 1 : 0;
+        if (!batched_fft_supported(q.p)) {
+            SingleFft sf{q.p, tw, {}, {}};
+            sf.fwd[0] = FftJob<float>{(const float*)q.A, Ah, q.m, q.n, q.n, lda, pack};
+            sf.fwd[1] = FftJob<float>{(const float*)q.B, Bh, q.n, q.s, q.s, ldb, pack};
+            sf.inv = FftJob<float>{Ch, (float*)q.C, q.m, q.s, ldc, q.s};
+            H->single.push_back(sf);
+        }
         H->fwd_jobs.push_back(BatchFftJob{(const float*)q.A, Ah, tw.f32, q.m, q.n, q.n, lda, q.p, pol, pack, 0});
         H->fwd_jobs.push_back(BatchFftJob{(const float*)q.B, Bh, tw.f32, q.n, q.s, q.s, ldb, q.p, pol, pack, 0});
         H->inv_jobs.push_back(BatchFftJob{Ch, (float*)q.C, tw.f32, q.m, q.s, ldc, q.s, q.p, pol, 0, 0});
@@ -345,10 +363,13 @@ int build_lists(int count, const qt_problem* probs, int prec, char* ws, const De
         H->probs.push_back(BatchGemmProb{FacewiseArgs<float>{Ah, Bh, Ch, q.m, q.n, q.s, q.p, lda, ldb, ldc},
                                          cfg, 0, 0, 0});
     }
+    // batched FFT items only for the lengths the batched kernel has
     for (int j = 0; j < (int)H->fwd_jobs.size(); ++j)
-        add_fft_items(H->fwd_items, j, (long)H->fwd_jobs[j].rows * H->fwd_jobs[j].cols);
+        if (batched_fft_supported(H->fwd_jobs[j].p))
+            add_fft_items(H->fwd_items, j, (long)H->fwd_jobs[j].rows * H->fwd_jobs[j].cols);
     for (int j = 0; j < (int)H->inv_jobs.size(); ++j)
-        add_fft_items(H->inv_items, j, (long)H->inv_jobs[j].rows * H->inv_jobs[j].cols);
+        if (batched_fft_supported(H->inv_jobs[j].p))
+            add_fft_items(H->inv_items, j, (long)H->inv_jobs[j].rows * H->inv_jobs[j].cols);
     auto by_p = [](const std::vector<BatchFftJob>& jobs) {
         return [&jobs](const BatchFftItem& x, const BatchFftItem& y) { return jobs[x.job].p > jobs[y.job].p; };
     };
@@ -428,6 +449,8 @@ int enqueue(const HostLists& H, char* ws, const DescLayout& L, int prec, hipStre
     for (const FftBucket& b : H.fwd_buckets)
         if (launch_batched_fft(false, b.p, b.pol, fj, fi + b.first, b.count, stream) != hipSuccess)
             return QT_ERR_HIP;
+    for (const SingleFft& sf : H.single)
+        if (launch_tube_fft<float>(sf.p, false, sf.fwd, 2, sf.tw, stream) != hipSuccess) return QT_ERR_HIP;
     for (int cfg = 0; cfg < detail::NUM_TILE_CFGS; ++cfg) {
         const int n = H.gcount[cfg];
         if (n && launch_batched_gemm(prec, cfg, pj, gi + H.gfirst[cfg], n, std::min(n, gemm_grid(prec, cfg)),
@@ -437,6 +460,8 @@ int enqueue(const HostLists& H, char* ws, const DescLayout& L, int prec, hipStre
     for (const FftBucket& b : H.inv_buckets)
         if (launch_batched_fft(true, b.p, b.pol, ij, ii + b.first, b.count, stream) != hipSuccess)
             return QT_ERR_HIP;
+    for (const SingleFft& sf : H.single)
+        if (launch_tube_fft<float>(sf.p, true, &sf.inv, 1, sf.tw, stream) != hipSuccess) return QT_ERR_HIP;
     return QT_OK;
 }
 
@@ -480,7 +505,7 @@ int validate(int count, const qt_problem* probs, int prec, void* ws, size_t ws_b
     }
     if (prec != QT_FP32 && prec != QT_SPLIT_BF16) return QT_ERR_UNSUPPORTED;
     for (int i = 0; i < count; ++i)
-        if (!batched_fft_supported(probs[i].p)) return QT_ERR_UNSUPPORTED;
+        if (probs[i].p > QT_MAX_P) return QT_ERR_UNSUPPORTED;
     return QT_OK;
 }
 

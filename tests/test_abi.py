@@ -274,9 +274,10 @@ def test_batched_rejects_bad_args():
     assert nat.qt_tprod_batched(2, two, F, W_, 1 << 30, None) == nat.QT_ERR_INVALID_ARG
     cross = nat.make_problems([(8, 8, 8, 8, A_, B_, C_), (8, 8, 8, 8, C_, B_, C_ + (1 << 20))])
     assert nat.qt_tprod_batched(2, cross, F, W_, 1 << 30, None) == nat.QT_ERR_INVALID_ARG
-    # shared inputs are fine; unsupported p or precision is reported as such
-    prime = nat.make_problems([(8, 8, 8, 11, A_, B_, C_)])
-    assert nat.qt_tprod_batched(1, prime, F, W_, 1 << 30, None) == nat.QT_ERR_UNSUPPORTED
+    # shared inputs are fine; p beyond QT_MAX_P or an unsupported precision is
+    # reported as such (every p up to QT_MAX_P is served)
+    big_p = nat.make_problems([(8, 8, 8, nat.QT_MAX_P + 1, A_, B_, C_)])
+    assert nat.qt_tprod_batched(1, big_p, F, W_, 1 << 40, None) == nat.QT_ERR_UNSUPPORTED
     assert nat.qt_tprod_batched(1, probs, nat.QT_FP64, W_, 1 << 30, None) == nat.QT_ERR_UNSUPPORTED
     st, plan = nat.qt_batched_plan_create(0, probs, F, W_, ws, None)
     assert st == nat.QT_ERR_INVALID_ARG and plan is None

@@ -58,6 +58,36 @@ def test_batched_matches_single_calls():
 
 
 @pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_batched_any_p(prec):
+    """Lengths without a batched FFT kernel (primes, p > 64, Bluestein and
+    register single-problem transforms) mixed with batched ones, in one call
+    and in a plan replayed twice: every replay bit-identical to the one-shot
+    call, and each problem against the oracle."""
+    rng = np.random.Generator(np.random.PCG64(19))
+    ps = [11, 8, 31, 97, 30, 100, 61, 128, 13, 45]
+    batch = []
+    for i, p in enumerate(ps):
+        m, n, s = (int(x) for x in rng.integers(5, 90, 3))
+        batch.append((synth.quat_tensor(m, n, p, seed=19000 + 2 * i),
+                      synth.quat_tensor(n, s, p, seed=19001 + 2 * i)))
+    As = [to_dev(A) for A, _ in batch]
+    Bs = [to_dev(B) for _, B in batch]
+    print(f"batched any-p {prec}: p = {ps}", flush=True)
+    Cs = tprod_batched(As, Bs, prec)
+    plan = BatchedPlan(As, Bs, prec)
+    try:
+        for _ in range(2):
+            outs = plan.launch()
+            torch.cuda.synchronize()
+            for (A64, B64), A, B, C, Cp in zip(batch, As, Bs, Cs, outs):
+                assert torch.equal(C, Cp)
+                e = rel_err(to_np(C), oracle.tprod_faces(A64, B64))
+                assert e <= TOLS[prec], (A64.shape, e)
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
 def test_plan_replays_track_inputs(prec):
     """Replay the captured graph several times with eager work and syncs in
     between; every replay must equal the eager single-call results."""
