@@ -87,9 +87,10 @@ typedef enum {
     QT_SPLIT_FP16 = 2,  /* as QT_SPLIT_BF16 with fp16 hi+lo; operands scaled by a
                            power of two per frequency (A^[f]) and per frequency
                            pair (B^[f], B^[-f]) computed on the device.  Served
-                           by qt_tprod only: the scales belong to one product's
-                           operands, so qt_fourier_tprod, qt_tprod_backward,
-                           qt_tprod_batched / qt_batched_plan_create,
+                           by qt_tprod, qt_tprod_noalloc and qt_tprod_backward
+                           (each product computes the scales of its own
+                           operands); qt_fourier_tprod (its operands are the
+                           caller's), qt_tprod_batched / qt_batched_plan_create,
                            qt_tprod_complex and qt_tprod_real return
                            QT_ERR_UNSUPPORTED for it */
     QT_FP64 = 3,        /* every step in double (small problems, validation) */
@@ -308,7 +309,9 @@ size_t qt_backward_workspace_size(int m, int n, int s, int p, qt_precision preci
  * G = A * B - T these are dL/dA and dL/dB of the real components.  Either of
  * dA, dB may be NULL to skip it.  Computed in the Fourier domain with the
  * same frequency coupling as the forward product (bcirc(A * B) =
- * bcirc(A) bcirc(B), proof of Theorem 5.1). */
+ * bcirc(A) bcirc(B), proof of Theorem 5.1).  All four precisions; with
+ * QT_SPLIT_FP16 each of the two products scales its own operands (G is
+ * transformed twice when both adjoints are asked for). */
 qt_status qt_tprod_backward(int m, int n, int s, int p,
                       const void* A, const void* B, const void* G,
                       void* dA, void* dB,

@@ -193,9 +193,16 @@ int run_tprod(int m, int n, int s, int p, const T* A, const T* B, T* C, int prec
 //   Y  = B^H (s x n x p, dense)      Z  = A^H (n x m x p, dense)
 //   G^ (m x s, row stride ld(s))     Y^ (s x n, ld(n))     Z^ (n x m, ld(m))
 //   dA^ (m x n, ld(n))               dB^ (n x s, ld(s))
+// Split-fp16 adds a second transform of G (each product scales and rewrites
+// its operands in place, and G^ is an operand of both) and the scales and
+// max-abs partials of the two products.
 struct BackwardLayout {
-    size_t y, z, gh, yh, zh, dah, dbh, total;
+    size_t y, z, gh, yh, zh, dah, dbh, gh2, sc1, sc2, total;
 };
+
+size_t fp16_scale_floats(long rows, long k, long cols, long p) {
+    return (size_t)p * (2 + qt::fp16_partial_blocks(rows, k) + qt::fp16_partial_blocks(k, cols));
+}
 
 BackwardLayout backward_layout(long m, long n, long s, long p, int prec) {
     BackwardLayout L{};
@@ -208,8 +215,32 @@ BackwardLayout backward_layout(long m, long n, long s, long p, int prec) {
     L.zh = take(fourier_bytes(n, m, p, prec));
     L.dah = take(fourier_bytes(m, n, p, prec));
     L.dbh = take(fourier_bytes(n, s, p, prec));
+    if (prec == QT_SPLIT_FP16) {
+        L.gh2 = take(fourier_bytes(m, s, p, prec));
+        L.sc1 = take(sizeof(float) * fp16_scale_floats(m, s, n, p));   // dA = G * B^H
+        L.sc2 = take(sizeof(float) * fp16_scale_floats(n, m, s, p));   // dB = A^H * G
+    }
     L.total = off;
     return L;
+}
+
+// One split-fp16 product on FP32 Fourier operands: per-frequency scales,
+// scaled fp16 words written over both operands (narrow products read the
+// FP32 values), the product, scales undone at the store.
+int fp16_product(const FacewiseArgs<float>& fa, float* sc, hipStream_t stream) {
+    float* scales = sc;
+    float* partials = sc + 2 * (size_t)fa.p;
+    int st = hip_status(qt::launch_fp16_scales(fa, partials, scales, stream));
+    if (st != QT_OK) return st;
+    if (fa.s > qt::kNarrowMaxS) {
+        st = hip_status(qt::launch_fp16_words(const_cast<float*>(fa.Ah), fa.p, fa.m, fa.n, fa.lda, scales, stream));
+        if (st != QT_OK) return st;
+        st = hip_status(qt::launch_fp16_words(const_cast<float*>(fa.Bh), fa.p, fa.n, fa.s, fa.ldb, scales + fa.p,
+                                              stream));
+        if (st != QT_OK) return st;
+    }
+    return hip_status(qt::launch_facewise_f32(fa, QT_SPLIT_FP16, stream,
+                                              qt::choose_tile(fa.m, fa.n, fa.s, QT_SPLIT_FP16), scales));
 }
 
 // dA = G * B^H and dB = A^H * G: transpose-conjugate B and A, one FFT of G
@@ -247,6 +278,34 @@ int run_backward(int m, int n, int s, int p, const T* A, const T* B, const T* G,
         FftJob<T> f2[1] = {{Z, Zh, n, m, m, ldm, pack}};
         st = hip_status(qt::launch_tube_fft<T>(p, false, f2, 1, tw, stream));
         if (st != QT_OK) return st;
+    }
+    if constexpr (sizeof(T) == 4) {
+        if (prec == QT_SPLIT_FP16) {
+            // G^ is the left operand of dA and the right one of dB, each
+            // rewritten in place with its own scales: dB gets a second copy
+            T* Gb = Gh;
+            if (dA && dB) {
+                Gb = reinterpret_cast<T*>(ws + L.gh2);
+                FftJob<T> f3[1] = {{G, Gb, m, s, s, lds, 0}};
+                st = hip_status(qt::launch_tube_fft<T>(p, false, f3, 1, tw, stream));
+                if (st != QT_OK) return st;
+            }
+            if (dA) {
+                st = fp16_product(FacewiseArgs<T>{Gh, Yh, dAh, m, s, n, p, lds, ldn, ldn},
+                                  reinterpret_cast<float*>(ws + L.sc1), stream);
+                if (st != QT_OK) return st;
+            }
+            if (dB) {
+                st = fp16_product(FacewiseArgs<T>{Zh, Gb, dBh, n, m, s, p, ldm, lds, lds},
+                                  reinterpret_cast<float*>(ws + L.sc2), stream);
+                if (st != QT_OK) return st;
+            }
+            FftJob<T> inv16[2];
+            int n16 = 0;
+            if (dA) inv16[n16++] = FftJob<T>{dAh, dA, m, n, ldn, n};
+            if (dB) inv16[n16++] = FftJob<T>{dBh, dB, n, s, lds, s};
+            return hip_status(qt::launch_tube_fft<T>(p, true, inv16, n16, tw, stream));
+        }
     }
     if (dA) {
         FacewiseArgs<T> fa{Gh, Yh, dAh, m, s, n, p, lds, ldn, ldn};
@@ -527,7 +586,7 @@ int backward_ws(int m, int n, int s, int p, const void* A, const void* B, const 
         if (dB && overlaps(dB, bb, ins[q], insz[q])) return QT_ERR_INVALID_ARG;
     }
     if (dA && dB && overlaps(dA, ab, dB, bb)) return QT_ERR_INVALID_ARG;
-    if (!p_supported(p, precision) || precision == QT_SPLIT_FP16) return QT_ERR_UNSUPPORTED;
+    if (!p_supported(p, precision)) return QT_ERR_UNSUPPORTED;
     if (!dA && !dB) return QT_OK;
     if (precision == QT_FP64)
         return run_backward<double>(m, n, s, p, (const double*)A, (const double*)B, (const double*)G,

@@ -354,9 +354,6 @@ class QTProd(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, A, B, precision="fp32"):
-        if _prec(precision) == nat.QT_SPLIT_FP16 and any(ctx.needs_input_grad[:2]):
-            raise ValueError("split_fp16 has no backward (its per-frequency scales are made "
-                             "for one product); use fp32 or split_bf16 when gradients are needed")
         ctx.precision = precision
         A, B = A.contiguous(), B.contiguous()
         ctx.save_for_backward(A, B)          # the contiguous tensors the backward needs

@@ -17,11 +17,11 @@ from gpu_util import rel_err, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
-TOLS = {"fp32": 1e-5, "split_bf16": 5e-5, "fp64": 1e-13}
-DT = {"fp32": torch.float32, "split_bf16": torch.float32, "fp64": torch.float64}
+TOLS = {"fp32": 1e-5, "split_bf16": 5e-5, "split_fp16": 5e-5, "fp64": 1e-13}
+DT = {"fp32": torch.float32, "split_bf16": torch.float32, "split_fp16": torch.float32, "fp64": torch.float64}
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16", "fp64"])
 @pytest.mark.parametrize("m,n,s,p", [(8, 8, 8, 8), (37, 21, 50, 5), (150, 40, 130, 12),
                                      (1, 1, 1, 1), (3, 70, 2, 7)])
 def test_backward_matches_oracle(prec, m, n, s, p):
@@ -35,16 +35,17 @@ def test_backward_matches_oracle(prec, m, n, s, p):
     assert ea <= TOLS[prec] and eb <= TOLS[prec]
 
 
-def test_backward_one_sided():
+@pytest.mark.parametrize("prec", ["fp32", "split_fp16"])
+def test_backward_one_sided(prec):
     m, n, s, p = 40, 24, 33, 6
     A = synth.quat_tensor(m, n, p, seed=41)
     B = synth.quat_tensor(n, s, p, seed=42)
     G = synth.quat_tensor(m, s, p, seed=43)
     rA, rB = oracle.adjoints(A, B, G)
-    dA, dB = tprod_backward(to_dev(A), to_dev(B), to_dev(G), need_dB=False)
-    assert dB is None and rel_err(to_np(dA), rA) <= 1e-5
-    dA, dB = tprod_backward(to_dev(A), to_dev(B), to_dev(G), need_dA=False)
-    assert dA is None and rel_err(to_np(dB), rB) <= 1e-5
+    dA, dB = tprod_backward(to_dev(A), to_dev(B), to_dev(G), prec, need_dB=False)
+    assert dB is None and rel_err(to_np(dA), rA) <= TOLS[prec]
+    dA, dB = tprod_backward(to_dev(A), to_dev(B), to_dev(G), prec, need_dA=False)
+    assert dA is None and rel_err(to_np(dB), rB) <= TOLS[prec]
 
 
 def test_adjoint_dot_identity_gpu():
@@ -61,7 +62,7 @@ def test_adjoint_dot_identity_gpu():
     assert abs(lhs - float((Bd * dB).sum())) <= 1e-11 * abs(lhs)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
 def test_autograd_function(prec):
     m, n, s, p = 60, 20, 44, 9
     A64 = synth.quat_tensor(m, n, p, seed=61)

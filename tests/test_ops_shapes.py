@@ -87,10 +87,3 @@ def test_batched_shapes():
     with pytest.raises(ValueError, match="one output tensor per problem"):
         ops.tprod_batched([A, A], [B, B], outs=[q(5, 3, 6)])
     raises_shape(ops.BatchedPlan, [A], [B], outs=[q(5, 2, 6)])
-
-
-def test_autograd_rejects_split_fp16_with_gradients():
-    A = q(5, 3, 4).requires_grad_()
-    B = q(5, 4, 6)
-    with pytest.raises(ValueError, match="split_fp16 has no backward"):
-        ops.qtprod(A, B, "split_fp16")
