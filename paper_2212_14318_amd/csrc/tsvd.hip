@@ -168,15 +168,21 @@ __device__ bool jacobi_pair(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool quat
 // for h, hq <= 64 K.
 template <typename T, typename V, int K>
 __device__ bool jacobi_pair_reg(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool quat, T tol, Acc negl2, int lane) {
-    V a0[K], a1[K], b0[K], b1[K];
+    // the rotation columns are loaded with the data columns (one memory
+    // round trip per pair); they are only written back if a rotation happens
+    V a0[K], a1[K], b0[K], b1[K], c0[K], c1[K], d0[K], d1[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) {
         const int k = lane + 64 * t;
-        const bool in = k < h;
+        const bool in = k < h, inq = k < hq;
         a0[t] = in ? xi[k] : V{0, 0};
         a1[t] = in ? xi[k + h] : V{0, 0};
         b0[t] = in ? xj[k] : V{0, 0};
         b1[t] = in ? xj[k + h] : V{0, 0};
+        c0[t] = inq ? qi[k] : V{0, 0};
+        c1[t] = inq ? qi[k + hq] : V{0, 0};
+        d0[t] = inq ? qj[k] : V{0, 0};
+        d1[t] = inq ? qj[k + hq] : V{0, 0};
     }
     Acc al = 0, be = 0, g1r = 0, g1i = 0, g2r = 0, g2i = 0;
 #pragma unroll
@@ -209,14 +215,14 @@ __device__ bool jacobi_pair_reg(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool 
     const Acc csd = Acc(1) / sqrt(Acc(1) + tt * tt);
     const T cs = T(csd), sn = T(csd * tt);
     auto rot = [&](V& u0, V& u1, V& w0, V& w1) {
-        V c0 = cmul(e1c, w0), c1 = cmul(e1c, w1);
+        V r0 = cmul(e1c, w0), r1 = cmul(e1c, w1);
         if (quat) {
-            c0 = cadd(c0, cmul(e2c, cneg(cconj(w1))));
-            c1 = cadd(c1, cmul(e2c, cconj(w0)));
+            r0 = cadd(r0, cmul(e2c, cneg(cconj(w1))));
+            r1 = cadd(r1, cmul(e2c, cconj(w0)));
         }
-        const V n0 = csub(cscale(u0, cs), cscale(c0, sn)), n1 = csub(cscale(u1, cs), cscale(c1, sn));
-        w0 = cadd(cscale(u0, sn), cscale(c0, cs));
-        w1 = cadd(cscale(u1, sn), cscale(c1, cs));
+        const V n0 = csub(cscale(u0, cs), cscale(r0, sn)), n1 = csub(cscale(u1, cs), cscale(r1, sn));
+        w0 = cadd(cscale(u0, sn), cscale(r0, cs));
+        w1 = cadd(cscale(u1, sn), cscale(r1, cs));
         u0 = n0;
         u1 = n1;
     };
@@ -230,25 +236,12 @@ __device__ bool jacobi_pair_reg(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool 
             xj[k] = b0[t];
             xj[k + h] = b1[t];
         }
-    }
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-        const int k = lane + 64 * t;
-        const bool in = k < hq;
-        a0[t] = in ? qi[k] : V{0, 0};
-        a1[t] = in ? qi[k + hq] : V{0, 0};
-        b0[t] = in ? qj[k] : V{0, 0};
-        b1[t] = in ? qj[k + hq] : V{0, 0};
-    }
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-        const int k = lane + 64 * t;
         if (k < hq) {
-            rot(a0[t], a1[t], b0[t], b1[t]);
-            qi[k] = a0[t];
-            qi[k + hq] = a1[t];
-            qj[k] = b0[t];
-            qj[k + hq] = b1[t];
+            rot(c0[t], c1[t], d0[t], d1[t]);
+            qi[k] = c0[t];
+            qi[k + hq] = c1[t];
+            qj[k] = d0[t];
+            qj[k + hq] = d1[t];
         }
     }
     return true;
