@@ -185,3 +185,42 @@ def test_fourier_tsvd_stage_matches_qt_tsvd(prec):
     assert torch.equal(sig, sig0) and torch.equal(U, U0) and torch.equal(V, V0)
     assert nat.qt_fourier_tsvd(m, n, p, Ah.data_ptr(), lda, Uh.data_ptr(), ldu, Vh.data_ptr(), ldv, sig.data_ptr(),
                                P, ws.data_ptr(), need - 1, stream) == nat.QT_ERR_INVALID_ARG
+
+
+def test_tsvd_full_workload_sampled():
+    """The benchmarked workload: t-SVD of the 256x256x64 colour-video-like
+    tensor (U[0,1), seed 2000).  sigma against the oracle's, S f-diagonal,
+    and A = U * S * V^H on 256 sampled entries, with U * S formed from S's
+    diagonal tubes and the entries of (U * S) * V^H computed one by one from
+    the definition."""
+    A64 = synth.config_inputs(2)[0]
+    _, p, m, n = A64.shape
+    U, S, V, sig = _run(A64, "fp32")
+    ref_sig = ots.tsvd(A64)[3]
+    assert np.abs(sig - ref_sig).max() <= 2e-5 * ref_sig.max()
+    k = min(m, n)
+    d = np.arange(k)
+    off = S.copy()
+    off[:2][:, :, d, d] = 0
+    assert np.abs(off).max() <= 2e-5 * ref_sig.max()
+    # U * S: column j of face f is sum_r U[:, f - r, :, j] * s_j[r] (S is f-diagonal, no j part)
+    s_tube = S[0][:, d, d] + 1j * S[1][:, d, d]             # (p, k) complex diagonal tubes
+    US = np.zeros((4, p, m, n))
+    for f in range(p):
+        for r in range(p):
+            u = U[:, (f - r) % p][:, :, :k]                   # (4, m, k)
+            c = s_tube[r]                                     # complex per column
+            # (a + b i + c j + d k)(x + y i) for quaternion u and complex c
+            a, b, cc, dd = u
+            x, y = c.real, c.imag
+            US[0, f, :, :k] += a * x - b * y
+            US[1, f, :, :k] += a * y + b * x
+            US[2, f, :, :k] += cc * x + dd * y
+            US[3, f, :, :k] += dd * x - cc * y
+    rng = np.random.Generator(np.random.PCG64(8600))
+    kk, ii, jj = rng.integers(0, p, 256), rng.integers(0, m, 256), rng.integers(0, n, 256)
+    got = oracle.tprod_entries(US, oracle.tconjT(V), kk, ii, jj)
+    ref = A64[:, kk, ii, jj]
+    err = float(np.sqrt(np.sum((got - ref) ** 2) / np.sum(ref ** 2)))
+    print(f"  full workload: sampled reconstruction {err:.2e}", flush=True)
+    assert err <= 2e-5
