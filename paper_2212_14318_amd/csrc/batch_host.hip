@@ -35,8 +35,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 // timing the batched FFT kernel of that length with both.
 struct TuneTable {
     bool done = false;
-    double alpha[NUM_TILE_CFGS] = {0, 0, 0};
-    double beta[NUM_TILE_CFGS] = {0, 0, 0};
+    double alpha[NUM_TILE_CFGS] = {};
+    double beta[NUM_TILE_CFGS] = {};
     int fft_pol[65] = {0};
 };
 
@@ -283,7 +283,7 @@ DescLayout desc_layout(int count, const qt_problem* probs) {
     for (int i = 0; i < count; ++i) {
         const qt_problem& q = probs[i];
         nfi += 2 * (((long)q.m * q.n + 255) / 256) + 2 * (((long)q.n * q.s + 255) / 256);
-        ngi += (long)q.p * ((q.m + 63) / 64) * ((q.s + 63) / 64);   // 64 x 64 is the smallest tile
+        ngi += (long)q.p * ((q.m + 31) / 32) * ((q.s + 63) / 64);   // 32 x 64 is the smallest tile
         nii += 2 * (((long)q.m * q.s + 255) / 256);
         tens += fourier_bytes(q.m, q.n, q.p) + fourier_bytes(q.n, q.s, q.p) + fourier_bytes(q.m, q.s, q.p);
     }
@@ -325,7 +325,7 @@ struct HostLists {
     std::vector<FftBucket> fwd_buckets, inv_buckets;
     std::vector<BatchGemmProb> probs;
     std::vector<BatchGemmItem> gitems;      // grouped by tile shape, longest first in each group
-    int gfirst[detail::NUM_TILE_CFGS] = {0, 0, 0}, gcount[detail::NUM_TILE_CFGS] = {0, 0, 0};
+    int gfirst[detail::NUM_TILE_CFGS] = {}, gcount[detail::NUM_TILE_CFGS] = {};
 };
 
 void add_fft_items(std::vector<BatchFftItem>& items, int job, long positions) {

@@ -49,6 +49,8 @@ const void* gemm_kernel(int precision, int cfg) {
         case 2 * TILE_64x128 + 1: return gemm_fn<1, TILE_64x128>();
         case 2 * TILE_64x64: return gemm_fn<0, TILE_64x64>();
         case 2 * TILE_64x64 + 1: return gemm_fn<1, TILE_64x64>();
+        case 2 * TILE_32x64: return gemm_fn<0, TILE_32x64>();
+        case 2 * TILE_32x64 + 1: return gemm_fn<1, TILE_32x64>();
         default: return nullptr;
     }
 }
@@ -84,6 +86,8 @@ hipError_t launch_batched_gemm(int precision, int cfg, const BatchGemmProb* prob
         case 2 * TILE_64x128 + 1: QT_GEMM_LAUNCH(1, TILE_64x128); break;
         case 2 * TILE_64x64: QT_GEMM_LAUNCH(0, TILE_64x64); break;
         case 2 * TILE_64x64 + 1: QT_GEMM_LAUNCH(1, TILE_64x64); break;
+        case 2 * TILE_32x64: QT_GEMM_LAUNCH(0, TILE_32x64); break;
+        case 2 * TILE_32x64 + 1: QT_GEMM_LAUNCH(1, TILE_32x64); break;
         default: return hipErrorInvalidValue;
     }
 #undef QT_GEMM_LAUNCH

@@ -364,6 +364,7 @@ hipError_t launch_facewise_f32(const FacewiseArgs<float>& a, int precision, hipS
         case TILE_128x64: return launch_cfg<TILE_128x64>(a, precision, scales, stream);
         case TILE_64x128: return launch_cfg<TILE_64x128>(a, precision, scales, stream);
         case TILE_64x64: return launch_cfg<TILE_64x64>(a, precision, scales, stream);
+        case TILE_32x64: return launch_cfg<TILE_32x64>(a, precision, scales, stream);
         default: return hipErrorInvalidValue;
     }
 }

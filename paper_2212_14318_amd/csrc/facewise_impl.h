@@ -105,8 +105,12 @@ __device__ __forceinline__ V8 neg8(V8 x) {
 
 // Tile shapes (MT x NT) compiled for both kernels; the id is what the
 // autotuner stores and what a batched work item carries.
-enum TileCfg { TILE_128x64 = 0, TILE_64x128 = 1, TILE_64x64 = 2, NUM_TILE_CFGS = 3 };
-__host__ __device__ constexpr int tile_mt(int cfg) { return cfg == TILE_128x64 ? 128 : 64; }
+// 32x64 cuts the row padding of small problems (m <= 32, or m just above a
+// multiple of 64); its FP32 form has two waves, its split forms four.
+enum TileCfg { TILE_128x64 = 0, TILE_64x128 = 1, TILE_64x64 = 2, TILE_32x64 = 3, NUM_TILE_CFGS = 4 };
+__host__ __device__ constexpr int tile_mt(int cfg) {
+    return cfg == TILE_128x64 ? 128 : cfg == TILE_32x64 ? 32 : 64;
+}
 __host__ __device__ constexpr int tile_nt(int cfg) { return cfg == TILE_64x128 ? 128 : 64; }
 // Every split tile (bf16 or fp16 words) splits 8 waves into two plane groups
 // (tile_v2's PG): each wave reads half the staged planes per chunk, which cuts
@@ -119,7 +123,8 @@ __host__ __device__ constexpr bool plane_groups(int mode, int cfg) { return mode
 // waves (2 x 2).  (A 64-wide tile stages 96 or 160 KB per workgroup, so one
 // workgroup fills a CU's LDS.)
 __host__ __device__ constexpr int tile_waves(int mode, int cfg) {
-    return (cfg == TILE_128x64 || plane_groups(mode, cfg)) ? 8 : 4;
+    return cfg == TILE_32x64 ? (plane_groups(mode, cfg) ? 4 : 2)
+                             : (cfg == TILE_128x64 || plane_groups(mode, cfg)) ? 8 : 4;
 }
 
 
