@@ -67,14 +67,28 @@ facewise_split_kernel(FacewiseArgs<float> a, TileGrid tg, const float* __restric
     tile_v2<MODE, MT, NT, tile_waves(MODE, CFG), plane_groups(MODE, CFG)>(a, f, tm * MT, tn * NT, sa, sb, sm);
 }
 
-// ---------------------------------------------------------------- FP64 VALU
-// Plain 16 x 16 tiled kernel: one output element (all four planes) per thread.
-__global__ void __launch_bounds__(256) facewise_f64_valu(FacewiseArgs<double> a) {
-    __shared__ double sA[4][16][17];
-    __shared__ double sB[8][16][17];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int row = blockIdx.y * 16 + ty;
-    const int col = blockIdx.x * 16 + tx;
+// ---------------------------------------------------------------- FP64 MFMA
+// 64 x 64 tile of all four output planes per workgroup on
+// v_mfma_f64_16x16x4_f64 (4 waves in a 2 x 2 grid, each wave 32 x 32 as 2 x 2
+// blocks of 16 x 16).  Operand layout of that instruction (checked on the
+// device): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; register r of
+// the accumulator holds D[4 r + l / 16][l % 16].  Each output plane is the
+// signed sum of four real products (the expansion above), so a 4-deep k-step
+// issues 16 MFMAs per 16 x 16 block; the signs are taken from negated A
+// fragments.  Chunks of 8 k of the four A planes and the eight B planes (f and
+// -f) go through LDS with out-of-range entries stored as zero (any lda, ldb:
+// the Fourier rows of an FP64 product need no alignment).
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kF64T = 64, kF64K = 8;
+constexpr int kF64ALd = kF64K + 1;          // A chunk row stride (doubles): 16 lanes, 16 distinct bank pairs
+constexpr int kF64BLd = kF64T + 2;          // B chunk row stride (doubles)
+
+__global__ void __launch_bounds__(256, 2) facewise_f64_kernel(FacewiseArgs<double> a) {
+    __shared__ double sA[4][kF64T * kF64ALd];
+    __shared__ double sB[8][kF64K * kF64BLd];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int n0 = blockIdx.x * kF64T, m0 = blockIdx.y * kF64T;
     const int f = blockIdx.z;
     const int g = (a.p - f) % a.p;
     const size_t pa = (size_t)a.p * a.m * a.lda;
@@ -83,40 +97,103 @@ __global__ void __launch_bounds__(256) facewise_f64_valu(FacewiseArgs<double> a)
     const double* Af = a.Ah + (size_t)f * a.m * a.lda;
     const double* Bf = a.Bh + (size_t)f * a.n * a.ldb;
     const double* Bg = a.Bh + (size_t)g * a.n * a.ldb;
-    double c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-    for (int k0 = 0; k0 < a.n; k0 += 16) {
-        const int ka = k0 + tx, kb = k0 + ty;
+    const int li = lane & 15, lk = lane >> 4;
+
+    v4d acc[4][2][2];
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            sA[c][ty][tx] = (row < a.m && ka < a.n) ? Af[c * pa + (size_t)row * a.lda + ka] : 0.0;
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            sB[c][ty][tx] = (kb < a.n && col < a.s) ? Bf[c * pb + (size_t)kb * a.ldb + col] : 0.0;
-            sB[4 + c][ty][tx] = (kb < a.n && col < a.s) ? Bg[c * pb + (size_t)kb * a.ldb + col] : 0.0;
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) acc[c][mb][nb] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    for (int k0 = 0; k0 < a.n; k0 += kF64K) {
+        __syncthreads();                     // the previous chunk is consumed
+        // A: 64 rows x 8 k per plane (two entries per thread and plane)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int idx = tid + 256 * j;
+            const int r = idx >> 3, k = idx & 7;
+            const bool ok = (m0 + r < a.m) && (k0 + k < a.n);
+            const size_t off = (size_t)(m0 + r) * a.lda + k0 + k;
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) sA[pl][r * kF64ALd + k] = ok ? Af[pl * pa + off] : 0.0;
+        }
+        // B: 8 k x 64 columns per plane, staged at f (planes 0..3) and at -f (4..7)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int idx = tid + 256 * j;
+            const int k = idx >> 6, c = idx & 63;
+            const bool ok = (k0 + k < a.n) && (n0 + c < a.s);
+            const size_t off = (size_t)(k0 + k) * a.ldb + n0 + c;
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) {
+                sB[pl][k * kF64BLd + c] = ok ? Bf[pl * pb + off] : 0.0;
+                sB[4 + pl][k * kF64BLd + c] = ok ? Bg[pl * pb + off] : 0.0;
+            }
         }
         __syncthreads();
+#pragma unroll 1
+        for (int ks = 0; ks < kF64K / 4; ++ks) {
+            const int k = 4 * ks + lk;
+            double ar1[2], ai1[2], ar2[2], ai2[2];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const double ar1 = sA[0][ty][k], ai1 = sA[1][ty][k];
-            const double ar2 = sA[2][ty][k], ai2 = sA[3][ty][k];
-            const double br1f = sB[0][k][tx], bi1f = sB[1][k][tx];
-            const double br2f = sB[2][k][tx], bi2f = sB[3][k][tx];
-            const double br1g = sB[4][k][tx], bi1g = sB[5][k][tx];
-            const double br2g = sB[6][k][tx], bi2g = sB[7][k][tx];
-            c0 += ar1 * br1f - ai1 * bi1f - ar2 * br2g - ai2 * bi2g;
-            c1 += ar1 * bi1f + ai1 * br1f + ar2 * bi2g - ai2 * br2g;
-            c2 += ar1 * br2f - ai1 * bi2f + ar2 * br1g + ai2 * bi1g;
-            c3 += ar1 * bi2f + ai1 * br2f + ai2 * br1g - ar2 * bi1g;
+            for (int mb = 0; mb < 2; ++mb) {
+                const int r = wm * 32 + mb * 16 + li;
+                ar1[mb] = sA[0][r * kF64ALd + k];
+                ai1[mb] = sA[1][r * kF64ALd + k];
+                ar2[mb] = sA[2][r * kF64ALd + k];
+                ai2[mb] = sA[3][r * kF64ALd + k];
+            }
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const int c = wn * 32 + nb * 16 + li;
+                double b[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) b[q] = sB[q][k * kF64BLd + c];
+                // b: B1r, B1i, B2r, B2i at f, then the same planes at -f
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb) {
+                    const double x1 = ar1[mb], y1 = ai1[mb], x2 = ar2[mb], y2 = ai2[mb];
+                    // Re C1 = Ar1 B1r - Ai1 B1i - Ar2 B2r(-f) - Ai2 B2i(-f)
+                    acc[0][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, b[0], acc[0][mb][nb], 0, 0, 0);
+                    acc[0][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y1, b[1], acc[0][mb][nb], 0, 0, 0);
+                    acc[0][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x2, b[6], acc[0][mb][nb], 0, 0, 0);
+                    acc[0][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y2, b[7], acc[0][mb][nb], 0, 0, 0);
+                    // Im C1 = Ar1 B1i + Ai1 B1r + Ar2 B2i(-f) - Ai2 B2r(-f)
+                    acc[1][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, b[1], acc[1][mb][nb], 0, 0, 0);
+                    acc[1][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1, b[0], acc[1][mb][nb], 0, 0, 0);
+                    acc[1][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(x2, b[7], acc[1][mb][nb], 0, 0, 0);
+                    acc[1][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y2, b[6], acc[1][mb][nb], 0, 0, 0);
+                    // Re C2 = Ar1 B2r - Ai1 B2i + Ar2 B1r(-f) + Ai2 B1i(-f)
+                    acc[2][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, b[2], acc[2][mb][nb], 0, 0, 0);
+                    acc[2][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y1, b[3], acc[2][mb][nb], 0, 0, 0);
+                    acc[2][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(x2, b[4], acc[2][mb][nb], 0, 0, 0);
+                    acc[2][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(y2, b[5], acc[2][mb][nb], 0, 0, 0);
+                    // Im C2 = Ar1 B2i + Ai1 B2r + Ai2 B1r(-f) - Ar2 B1i(-f)
+                    acc[3][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, b[3], acc[3][mb][nb], 0, 0, 0);
+                    acc[3][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(y1, b[2], acc[3][mb][nb], 0, 0, 0);
+                    acc[3][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(y2, b[4], acc[3][mb][nb], 0, 0, 0);
+                    acc[3][mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x2, b[5], acc[3][mb][nb], 0, 0, 0);
+                }
+            }
         }
-        __syncthreads();
     }
-    if (row < a.m && col < a.s) {
-        double* Cf = a.Ch + (size_t)f * a.m * a.ldc + (size_t)row * a.ldc + col;
-        Cf[0] = c0;
-        Cf[pc] = c1;
-        Cf[2 * pc] = c2;
-        Cf[3 * pc] = c3;
-    }
+    double* Cf = a.Ch + (size_t)f * a.m * a.ldc;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            const int col = n0 + wn * 32 + nb * 16 + li;
+            if (col >= a.s) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * 32 + mb * 16 + 4 * r + lk;
+                if (row >= a.m) continue;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) Cf[c * pc + (size_t)row * a.ldc + col] = acc[c][mb][nb][r];
+            }
+        }
 }
 
 // ------------------------------------------------------ complex products
@@ -395,8 +472,8 @@ hipError_t launch_facewise_cx(const FacewiseArgs<float>& a, int precision, hipSt
 }
 
 hipError_t launch_facewise_f64(const FacewiseArgs<double>& a, hipStream_t stream) {
-    hipLaunchKernelGGL(facewise_f64_valu, dim3((a.s + 15) / 16, (a.m + 15) / 16, a.p), dim3(256), 0,
-                       stream, a);
+    hipLaunchKernelGGL(facewise_f64_kernel, dim3((a.s + kF64T - 1) / kF64T, (a.m + kF64T - 1) / kF64T, a.p),
+                       dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 
