@@ -112,15 +112,18 @@ __host__ __device__ constexpr int tile_mt(int cfg) {
     return cfg == TILE_128x64 ? 128 : cfg == TILE_32x64 ? 32 : 64;
 }
 __host__ __device__ constexpr int tile_nt(int cfg) { return cfg == TILE_64x128 ? 128 : 64; }
-// Every split tile (bf16 or fp16 words) splits 8 waves into two plane groups
+// The split tiles (bf16 or fp16 words) split 8 waves into two plane groups
 // (tile_v2's PG): each wave reads half the staged planes per chunk, which cuts
-// LDS fragment reads and unpacking by a third.
-__host__ __device__ constexpr bool plane_groups(int mode, int cfg) { return mode != 0 && cfg >= 0; }
+// LDS fragment reads and unpacking by a third.  Not the 64 x 128 split tile:
+// with two waves per SIMD its 128 accumulator registers plus the group's
+// fragments and DMA addresses exceed 256 VGPRs and spill, so it runs 4 waves
+// of 512 registers each.
+__host__ __device__ constexpr bool plane_groups(int mode, int cfg) { return mode != 0 && cfg != TILE_64x128; }
 // Waves per workgroup of a tile shape and mode (0 FP32, 1 split bf16, 2 split
-// fp16): 8 waves for the 128 x 64 tile (4 x 2, each 32 x 32) and for every
-// split tile (two plane groups of 2 x 2), so that two waves share a SIMD
-// and hide each other's LDS and VALU latency; the other 64-wide tiles run 4
-// waves (2 x 2).  (A 64-wide tile stages 96 or 160 KB per workgroup, so one
+// fp16): 8 waves for the 128 x 64 tile (4 x 2, each 32 x 32) and for the
+// plane-group split tiles (two groups of 2 x 2), so that two waves share a
+// SIMD and hide each other's LDS and VALU latency; the other 64-wide tiles run
+// 4 waves (2 x 2).  (A 64-wide tile stages 96 or 160 KB per workgroup, so one
 // workgroup fills a CU's LDS.)
 __host__ __device__ constexpr int tile_waves(int mode, int cfg) {
     return cfg == TILE_32x64 ? (plane_groups(mode, cfg) ? 4 : 2)
