@@ -31,6 +31,7 @@ PEAK_TFLOPS = {"fp32": 157.3, "split_bf16": 2516.6, "split_fp16": 2516.6, "fp64"
 PEAK_HBM_GBPS = 8000.0
 
 WORKLOADS = {
+    "c1": dict(cfg=1, desc="A, B 8x8x8 quaternion, components N(0,1) (seeds 1000/1001)"),
     "c2": dict(cfg=2, desc="A, B 256x256x64 quaternion, components U[0,1) (seeds 2000/2001)"),
     "c3": dict(cfg=3, desc="A, B 1024x1024x32 quaternion, components N(0,1) (seeds 3000/3001)"),
     "c5": dict(cfg=5, desc="A 512x64x100, B 64x512x100 quaternion, components N(0,1) "
@@ -123,7 +124,7 @@ def parse():
     ap.add_argument("--backward", action="store_true",
                     help="c5: time forward + hand-written backward instead of the forward alone")
     ap.add_argument("--p", type=int, default=0,
-                    help="c2 / c3: draw the inputs with this many faces instead (same shapes, seeds and "
+                    help="c1 / c2 / c3: draw the inputs with this many faces instead (same shapes, seeds and "
                          "distribution), e.g. a prime p for the Bluestein transforms")
     ap.add_argument("--no-extras", action="store_true",
                     help="default workload only: skip the short batch / backward / t-SVD runs")
@@ -170,8 +171,8 @@ def main():
         return bench_complex(args, wl, dev, stream, real=args.workload == "real")
     t0 = time.time()
     if args.p:
-        if cfg not in (2, 3):
-            print("bench.py: --p applies to the c2 and c3 workloads", file=sys.stderr)
+        if cfg not in (1, 2, 3):
+            print("bench.py: --p applies to the c1, c2 and c3 workloads", file=sys.stderr)
             sys.exit(2)
         c = synth.CONFIGS[cfg]
         A64 = synth.quat_tensor(c["m"], c["n"], args.p, 1000 * cfg, c["dist"])
@@ -184,19 +185,27 @@ def main():
     _, p, m, n = A64.shape
     s = B64.shape[3]
     log(f"[bench] inputs {args.workload} m={m} n={n} s={s} p={p} drawn in {time.time() - t0:.1f}s")
-    A = torch.from_numpy(A64).to(dev, torch.float32)
-    B = torch.from_numpy(B64).to(dev, torch.float32)
     lda, ldb = nat.qt_fourier_ld(n), nat.qt_fourier_ld(s)
-    Ah = torch.empty((4, p, m, lda), dtype=torch.float32, device=dev)
-    Bh = torch.empty((4, p, n, ldb), dtype=torch.float32, device=dev)
-    Ch = torch.empty((4, p, m, ldb), dtype=torch.float32, device=dev)
-    C = torch.empty((4, p, m, s), dtype=torch.float32, device=dev)
-    # input/output sets rotated from step to step so that the spatial tensors of
-    # a small workload are not still in the 256 MB Infinity Cache from the
-    # previous step (at least 768 MiB of A, B, C across the sets)
-    set_bytes = (A.numel() + B.numel() + C.numel()) * 4
-    nsets = max(1, -(-(768 << 20) // set_bytes))
-    bufs = [(A, B, C)] + [(A.clone(), B.clone(), torch.empty_like(C)) for _ in range(nsets - 1)]
+
+    def make_buffers(dt):
+        """Inputs in the dtype of a precision (FP64 for fp64, else FP32), their
+        Fourier buffers, and input/output sets rotated from step to step so
+        that the spatial tensors of a small workload are not still in the
+        256 MB Infinity Cache from the previous step (at least 768 MiB of A, B,
+        C across the sets, at most 16 sets)."""
+        A = torch.from_numpy(A64).to(dev, dt)
+        B = torch.from_numpy(B64).to(dev, dt)
+        C = torch.empty((4, p, m, s), dtype=dt, device=dev)
+        set_bytes = (A.numel() + B.numel() + C.numel()) * A.element_size()
+        nsets = min(16, max(1, -(-(768 << 20) // set_bytes)))
+        return dict(
+            bufs=[(A, B, C)] + [(A.clone(), B.clone(), torch.empty_like(C)) for _ in range(nsets - 1)],
+            nsets=nsets,
+            Ah=torch.empty((4, p, m, lda), dtype=dt, device=dev),
+            Bh=torch.empty((4, p, n, ldb), dtype=dt, device=dev),
+            Ch=torch.empty((4, p, m, ldb), dtype=dt, device=dev))
+
+    cur = make_buffers(torch.float32)
     f_gemm, f_fft = flops(m, n, s, p)
     F = f_gemm + f_fft
     fft_fwd_bytes = 32.0 * p * (m * n + n * s)       # read + write 16 B per quaternion
@@ -214,7 +223,8 @@ def main():
     def stage_calls(prec_id, ev, k=0):
         # forward transforms in the operand format of the precision (split-bf16:
         # hi/lo words), product, inverse transform of the FP32 product
-        A, B, C = bufs[k % nsets]
+        A, B, C = cur["bufs"][k % cur["nsets"]]
+        Ah, Bh, Ch = cur["Ah"], cur["Bh"], cur["Ch"]
         st = nat.qt_tube_fft(m, n, p, A.data_ptr(), n, Ah.data_ptr(), lda, 0, prec_id, sh)
         nat.check(st, "qt_tube_fft(A)")
         st = nat.qt_tube_fft(n, s, p, B.data_ptr(), s, Bh.data_ptr(), ldb, 0, prec_id, sh)
@@ -224,13 +234,21 @@ def main():
                                   Ch.data_ptr(), ldb, prec_id, sh)
         nat.check(st, "qt_fourier_tprod")
         ev[1].record(stream)
-        st = nat.qt_tube_fft(m, s, p, Ch.data_ptr(), ldb, C.data_ptr(), s, 1, nat.QT_FP32, sh)
+        inv_id = nat.QT_FP64 if prec_id == nat.QT_FP64 else nat.QT_FP32
+        st = nat.qt_tube_fft(m, s, p, Ch.data_ptr(), ldb, C.data_ptr(), s, 1, inv_id, sh)
         nat.check(st, "qt_tube_fft(C^, inverse)")
 
     results = {}
     precs = [x for x in args.precisions.split(",") if x]
     for prec in precs:
         prec_id = nat.PRECISIONS[prec]
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        if cur["Ah"].dtype != dt:
+            cur = None
+            torch.cuda.empty_cache()
+            cur = make_buffers(dt)
+        bufs, nsets = cur["bufs"], cur["nsets"]
+        A, B, C = bufs[0]
         # check the staged path against the single entry point once (untimed)
         ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         try:
