@@ -80,7 +80,18 @@ struct TsvdArgs {
     int m, n, p, lda, ldu, ldv;
 };
 
-// Per-pair scratch layout (complex entries), for r = max(m, n), c = min(m, n):
+// State of one frequency pair between the kernels of the block sweeps.
+struct PairHdr {
+    double scale;           // power of two applied to the pair's matrix
+    double negl2;           // squared column norm below which a column is rounding noise
+    int done;               // a whole sweep applied no rotation
+    int rot[2];             // sweep s applied a rotation (slot s & 1)
+    int pad;
+};
+constexpr size_t kHdrBytes = 256;
+
+// Per-pair scratch layout, for r = max(m, n), c = min(m, n): the header,
+// then (complex entries)
 //   X   2c columns of 2r   (columns of chi_f(A) or chi_f(A)^*)
 //   Q   2c columns of 2c   (accumulated rotations)
 //   L   2r columns of 2r   (left vectors in rank order, then completed)
@@ -89,7 +100,7 @@ template <typename T>
 size_t pair_scratch_bytes(int m, int n) {
     const size_t r = m > n ? m : n, c = m > n ? n : m;
     const size_t e = 2 * c * 2 * r + 2 * c * 2 * c + 2 * r * 2 * r + 3 * r;
-    return (e * sizeof(typename Cx<T>::type) + 255) & ~(size_t)255;
+    return kHdrBytes + ((e * sizeof(typename Cx<T>::type) + 255) & ~(size_t)255);
 }
 
 // Position of player q in round t of the circle method over nup players
@@ -270,32 +281,60 @@ __device__ void write_slot(T* Yh, int ld, int p, int half, int f, int g, int slo
     }
 }
 
+// Geometry of frequency pair f: which matrix is orthogonalised and where its
+// scratch lives.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) tsvd_pair_kernel(TsvdArgs<T> a) {
+struct PairView {
     using V = typename Cx<T>::type;
-    __shared__ T s_sig[2 * kMaxMin];
-    __shared__ int s_perm[2 * kMaxMin];
-    __shared__ unsigned char s_ok[2 * kMaxMax];
-    __shared__ V s_w[2 * kMaxMax];
-    __shared__ Acc s_red[kWaves];
-    __shared__ int s_flag;
+    int f, g;
+    bool quat, tall;
+    int r, c, nu, nL, R, Rq;
+    PairHdr* hdr;
+    V *X, *Q, *L, *coef, *coef2;
+};
 
+template <typename T>
+__device__ __forceinline__ PairView<T> pair_view(const TsvdArgs<T>& a, int f) {
+    using V = typename Cx<T>::type;
+    PairView<T> v;
+    v.f = f;
+    v.g = (a.p - f) % a.p;
+    v.quat = f == v.g;
+    v.tall = a.m >= a.n;
+    v.r = v.tall ? a.m : a.n;
+    v.c = v.tall ? a.n : a.m;
+    v.nu = v.quat ? v.c : 2 * v.c;        // Jacobi units (columns, or quaternion columns)
+    v.nL = v.quat ? v.r : 2 * v.r;        // left-side slots
+    v.R = 2 * v.r;
+    v.Rq = 2 * v.c;
+    char* base = a.pairs + (size_t)f * a.pair_bytes;
+    v.hdr = reinterpret_cast<PairHdr*>(base);
+    v.X = reinterpret_cast<V*>(base + kHdrBytes);
+    v.Q = v.X + (size_t)2 * v.c * v.R;
+    v.L = v.Q + (size_t)2 * v.c * v.Rq;
+    v.coef = v.L + (size_t)2 * v.r * v.R;
+    v.coef2 = v.coef + (size_t)2 * v.r;
+    return v;
+}
+
+// Stopping threshold: the largest cosine left between two columns.
+template <typename T>
+__device__ __forceinline__ T jacobi_tol(int R) {
+    const T eps = sizeof(T) == 4 ? T(5.9604645e-8) : T(1.1102230246251565e-16);
+    return eps * sqrt((T)R);
+}
+
+// X <- the pair's matrix scaled by a power of two so that its largest entry
+// is in [0.5, 1) (the squared norms of the Jacobi steps then neither overflow
+// nor underflow), Q <- identity; the header gets the scale and the noise
+// level negl2 (tol^2 times the squared Frobenius norm: a column below it is
+// rounding noise of the whole matrix).  Whole workgroup.
+template <typename T>
+__device__ void pair_prep(const TsvdArgs<T>& a, const PairView<T>& pv, Acc* s_red, T& scale, Acc& negl2) {
+    using V = typename Cx<T>::type;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int f = blockIdx.x, p = a.p, m = a.m, n = a.n;
-    const int g = (p - f) % p;
-    const bool quat = f == g;
-    const bool tall = m >= n;
-    const int r = tall ? m : n, c = tall ? n : m;
-    const int nu = quat ? c : 2 * c;       // Jacobi units (columns, or quaternion columns)
-    const int nL = quat ? r : 2 * r;       // left-side slots
-    const int R = 2 * r, Rq = 2 * c;
-    V* X = reinterpret_cast<V*>(a.pairs + (size_t)f * a.pair_bytes);
-    V* Q = X + (size_t)2 * c * R;
-    V* L = Q + (size_t)2 * c * Rq;
-    V* coef = L + (size_t)2 * r * R;
-    V* coef2 = coef + (size_t)2 * r;
-
-    const size_t pl = (size_t)p * m * a.lda;
+    const int m = a.m, n = a.n, f = pv.f, g = pv.g;
+    const size_t pl = (size_t)a.p * m * a.lda;
     auto A1 = [&](int fr, int i, int j) {
         const size_t o = ((size_t)fr * m + i) * a.lda + j;
         return V{a.Ah[o], a.Ah[pl + o]};
@@ -306,7 +345,7 @@ __global__ void __launch_bounds__(kThreads) tsvd_pair_kernel(TsvdArgs<T> a) {
     };
     // entry k of unit u of the matrix whose columns are orthogonalised
     auto entry = [&](int u, int k) -> V {
-        if (tall) {   // column u of chi_f(A)
+        if (pv.tall) {   // column u of chi_f(A)
             if (u < n) return k < m ? A1(f, k, u) : cneg(cconj(A2(g, k - m, u)));
             return k < m ? A2(f, k, u - n) : cconj(A1(g, k - m, u - n));
         }
@@ -314,10 +353,7 @@ __global__ void __launch_bounds__(kThreads) tsvd_pair_kernel(TsvdArgs<T> a) {
         if (u < m) return k < n ? cconj(A1(f, u, k)) : cconj(A2(f, u, k - n));
         return k < n ? cneg(A2(g, u - m, k)) : A1(g, u - m, k - n);
     };
-
-    // scale the pair's matrix by a power of two so that its largest entry is
-    // in [0.5, 1): the squared norms of the Jacobi steps then neither
-    // overflow nor underflow
+    const int R = pv.R, Rq = pv.Rq, nu = pv.nu;
     T mx = 0;
     for (int e = tid; e < nu * R; e += kThreads) {
         const V v = entry(e / R, e % R);
@@ -329,48 +365,88 @@ __global__ void __launch_bounds__(kThreads) tsvd_pair_kernel(TsvdArgs<T> a) {
     mx = 0;
     for (int w = 0; w < kWaves; ++w) mx = fmax(mx, (T)s_red[w]);
     const int ex = (mx > 0 && isfinite(mx)) ? ilogb(mx) + 1 : 0;
-    const T scale = ldexp(T(1), -ex);
+    scale = ldexp(T(1), -ex);
     Acc fro = 0;
     for (int e = tid; e < nu * R; e += kThreads) {
         const V v = cscale(entry(e / R, e % R), scale);
-        X[e] = v;
+        pv.X[e] = v;
         fro += (Acc)v.x * v.x + (Acc)v.y * v.y;
     }
-    for (int e = tid; e < nu * Rq; e += kThreads) Q[e] = V{(e % Rq) == (e / Rq) ? T(1) : T(0), T(0)};
+    for (int e = tid; e < nu * Rq; e += kThreads) pv.Q[e] = V{(e % Rq) == (e / Rq) ? T(1) : T(0), T(0)};
     fro = wave_sum(fro);
     __syncthreads();
     if (lane == 0) s_red[wave] = fro;
     __syncthreads();
     fro = 0;
     for (int w = 0; w < kWaves; ++w) fro += s_red[w];
+    const T tol = jacobi_tol<T>(R);
+    negl2 = (Acc)tol * tol * fro;
+    if (tid == 0) {
+        pv.hdr->scale = (double)scale;
+        pv.hdr->negl2 = negl2;
+        pv.hdr->done = 0;
+        pv.hdr->rot[0] = 0;
+        pv.hdr->rot[1] = 0;
+    }
+}
 
-    // one-sided Jacobi sweeps, round-robin over disjoint unit pairs.  tol:
-    // the largest cosine left between two columns; negl: the norm below which
-    // a column is rounding noise of the whole matrix (sum of squares fro)
-    const T eps = sizeof(T) == 4 ? T(5.9604645e-8) : T(1.1102230246251565e-16);
-    const T tol = eps * sqrt((T)R);
-    const Acc negl2 = (Acc)tol * tol * fro;
+// One-sided Jacobi sweeps of one workgroup over all unit pairs, round-robin
+// over disjoint pairs, until a sweep applies no rotation.
+template <typename T>
+__device__ void pair_sweeps(const PairView<T>& pv, Acc negl2, int* s_flag) {
+    using V = typename Cx<T>::type;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nu = pv.nu, R = pv.R, Rq = pv.Rq, r = pv.r, c = pv.c;
+    const T tol = jacobi_tol<T>(R);
     const int nup = nu + (nu & 1);
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
         __syncthreads();
-        if (tid == 0) s_flag = 0;
+        if (tid == 0) *s_flag = 0;
         __syncthreads();
         for (int t = 0; t < nup - 1; ++t) {
             for (int q = wave; q < nup / 2; q += kWaves) {
                 const int i = circle(q, t, nup), j = circle(nup - 1 - q, t, nup);
                 if (i >= nu || j >= nu) continue;
-                V *xi = X + (size_t)i * R, *xj = X + (size_t)j * R;
-                V *qi = Q + (size_t)i * Rq, *qj = Q + (size_t)j * Rq;
+                V *xi = pv.X + (size_t)i * R, *xj = pv.X + (size_t)j * R;
+                V *qi = pv.Q + (size_t)i * Rq, *qj = pv.Q + (size_t)j * Rq;
                 const bool rotated =
-                    (r <= 64 && c <= 64)     ? jacobi_pair_reg<T, V, 1>(xi, xj, qi, qj, r, c, quat, tol, negl2, lane)
-                    : (r <= 256 && c <= 256) ? jacobi_pair_reg<T, V, 4>(xi, xj, qi, qj, r, c, quat, tol, negl2, lane)
-                                             : jacobi_pair<T, V>(xi, xj, qi, qj, r, c, quat, tol, negl2, lane);
-                if (rotated && lane == 0) s_flag = 1;
+                    (r <= 64 && c <= 64)     ? jacobi_pair_reg<T, V, 1>(xi, xj, qi, qj, r, c, pv.quat, tol, negl2, lane)
+                    : (r <= 256 && c <= 256) ? jacobi_pair_reg<T, V, 4>(xi, xj, qi, qj, r, c, pv.quat, tol, negl2, lane)
+                                             : jacobi_pair<T, V>(xi, xj, qi, qj, r, c, pv.quat, tol, negl2, lane);
+                if (rotated && lane == 0) *s_flag = 1;
             }
             __syncthreads();
         }
-        if (s_flag == 0) break;
+        if (*s_flag == 0) break;
     }
+}
+
+// Shared arrays of the last step.
+template <typename T>
+struct FinishSmem {
+    using V = typename Cx<T>::type;
+    T sig[2 * kMaxMin];
+    int perm[2 * kMaxMin];
+    unsigned char ok[2 * kMaxMax];
+    V w[2 * kMaxMax];
+    Acc red[kWaves];
+};
+
+// From the orthogonalised columns: singular values in descending order,
+// normalised left vectors (completed to an orthonormal basis), and both
+// vector sets placed at f and -f.  Whole workgroup.
+template <typename T>
+__device__ void pair_finish(const TsvdArgs<T>& a, const PairView<T>& pv, T scale, Acc negl2, FinishSmem<T>& sm) {
+    using V = typename Cx<T>::type;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int p = a.p, f = pv.f, g = pv.g, r = pv.r, c = pv.c, nu = pv.nu, nL = pv.nL, R = pv.R, Rq = pv.Rq;
+    const bool quat = pv.quat, tall = pv.tall;
+    V *X = pv.X, *Q = pv.Q, *L = pv.L, *coef = pv.coef, *coef2 = pv.coef2;
+    T* s_sig = sm.sig;
+    int* s_perm = sm.perm;
+    unsigned char* s_ok = sm.ok;
+    V* s_w = sm.w;
+    Acc* s_red = sm.red;
 
     // singular values (column norms) and their descending order
     for (int u = wave; u < nu; u += kWaves) {
@@ -486,6 +562,140 @@ __global__ void __launch_bounds__(kThreads) tsvd_pair_kernel(TsvdArgs<T> a) {
         write_slot<T, V>(Qh, ldq, p, c, f, g, slot(rho, c), Q + (size_t)s_perm[rho] * Rq, tid, kThreads);
 }
 
+// One workgroup per frequency pair, every step in one launch.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) tsvd_pair_kernel(TsvdArgs<T> a) {
+    __shared__ FinishSmem<T> sm;
+    __shared__ int s_flag;
+    const PairView<T> pv = pair_view(a, blockIdx.x);
+    T scale;
+    Acc negl2;
+    pair_prep(a, pv, sm.red, scale, negl2);
+    __syncthreads();
+    pair_sweeps(pv, negl2, &s_flag);
+    __syncthreads();
+    pair_finish(a, pv, scale, negl2, sm);
+}
+
+// ------------------------------------------------------------ block sweeps
+// For larger matrices the sweeps are spread over many workgroups per pair.
+// The units are cut into blocks of bs; in round t of a sweep, block pair q
+// of the circle schedule over the blocks goes to one workgroup, which stages
+// the data and rotation columns of its two blocks in LDS, applies the
+// rotations of every unit pair across the two blocks (and, in round 0, the
+// pairs within each block), and writes the columns back.  Every unit pair is
+// visited once per sweep, as in the single-workgroup order, with one global
+// read and write of a column per block pair instead of one per unit pair.
+// A sweep is one launch per round plus a check: a pair whose sweep applied no
+// rotation is done, and its workgroups return at once in later launches.
+constexpr size_t kBlockLds = 144 << 10;   // staged columns per workgroup
+constexpr int kBlockMinUnits = 128;       // smaller matrices stay in one workgroup
+constexpr int kBlockMaxSweeps = 32;
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) tsvd_prep_kernel(TsvdArgs<T> a) {
+    __shared__ Acc s_red[kWaves];
+    const PairView<T> pv = pair_view(a, blockIdx.x);
+    T scale;
+    Acc negl2;
+    pair_prep(a, pv, s_red, scale, negl2);
+}
+
+// grid: (block pairs of the longest schedule, frequency pairs)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) tsvd_round_kernel(TsvdArgs<T> a, int bs, int t, int sweep) {
+    using V = typename Cx<T>::type;
+    __shared__ __attribute__((aligned(16))) char s_cols[kBlockLds];
+    __shared__ int s_rot;
+    const PairView<T> pv = pair_view(a, blockIdx.y);
+    if (pv.hdr->done) return;
+    const int nu = pv.nu, nb = (nu + bs - 1) / bs, nbp = nb + (nb & 1);
+    const int q = blockIdx.x;
+    if (t >= nbp - 1 || q >= nbp / 2) return;      // a shorter schedule (quaternion pair)
+    const int I = circle(q, t, nbp), J = circle(nbp - 1 - q, t, nbp);
+    const int nI = I < nb ? min(bs, nu - I * bs) : 0;
+    const int nJ = J < nb ? min(bs, nu - J * bs) : 0;
+    if (t > 0 && (nI == 0 || nJ == 0)) return;      // within-block pairs go in round 0 only
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int R = pv.R, Rq = pv.Rq, nk = nI + nJ;
+    V* xs = reinterpret_cast<V*>(s_cols);            // staged unit k: xs + k R, qs + k Rq
+    V* qs = xs + (size_t)nk * R;
+    auto unit = [&](int k) { return k < nI ? I * bs + k : J * bs + (k - nI); };
+    for (int e = tid; e < nk * R; e += kThreads) xs[e] = pv.X[(size_t)unit(e / R) * R + e % R];
+    for (int e = tid; e < nk * Rq; e += kThreads) qs[e] = pv.Q[(size_t)unit(e / Rq) * Rq + e % Rq];
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    const T tol = jacobi_tol<T>(R);
+    const Acc negl2 = pv.hdr->negl2;
+    bool rot = false;
+    auto step = [&](int i, int j) {
+        rot |= jacobi_pair<T, V>(xs + (size_t)i * R, xs + (size_t)j * R, qs + (size_t)i * Rq,
+                                 qs + (size_t)j * Rq, pv.r, pv.c, pv.quat, tol, negl2, lane);
+    };
+    if (t == 0) {
+        // pairs within block I (staged 0 .. nI - 1) and within block J
+        // (nI .. nk - 1), both on the circle schedule, in the same rounds
+        const int pI = nI + (nI & 1), pJ = nJ + (nJ & 1);
+        const int rounds = (pI > pJ ? pI : pJ) - 1;
+        for (int tt = 0; tt < rounds; ++tt) {
+            const int hI = tt < pI - 1 ? pI / 2 : 0, hJ = tt < pJ - 1 ? pJ / 2 : 0;
+            for (int w = wave; w < hI + hJ; w += kWaves) {
+                int i, j;
+                if (w < hI) {
+                    i = circle(w, tt, pI);
+                    j = circle(pI - 1 - w, tt, pI);
+                    if (i >= nI || j >= nI) continue;
+                } else {
+                    const int v = w - hI;
+                    i = circle(v, tt, pJ);
+                    j = circle(pJ - 1 - v, tt, pJ);
+                    if (i >= nJ || j >= nJ) continue;
+                    i += nI;
+                    j += nI;
+                }
+                step(i, j);
+            }
+            __syncthreads();
+        }
+    }
+    // pairs across the blocks: in round tt, unit k of I meets unit
+    // (k + tt) mod bmax of J (disjoint within a round, all pairs over bmax rounds)
+    const int bmax = nI > nJ ? nI : nJ;
+    if (nI > 0 && nJ > 0) {
+        for (int tt = 0; tt < bmax; ++tt) {
+            for (int k = wave; k < bmax; k += kWaves) {
+                const int l = (k + tt) % bmax;
+                if (k < nI && l < nJ) step(k, nI + l);
+            }
+            __syncthreads();
+        }
+    }
+    if (rot && lane == 0) s_rot = 1;
+    __syncthreads();
+    if (!s_rot) return;
+    for (int e = tid; e < nk * R; e += kThreads) pv.X[(size_t)unit(e / R) * R + e % R] = xs[e];
+    for (int e = tid; e < nk * Rq; e += kThreads) pv.Q[(size_t)unit(e / Rq) * Rq + e % Rq] = qs[e];
+    if (tid == 0) pv.hdr->rot[sweep & 1] = 1;
+}
+
+// After sweep s: a pair whose sweep applied no rotation is done; the slot of
+// sweep s is cleared for sweep s + 2.
+template <typename T>
+__global__ void __launch_bounds__(256) tsvd_check_kernel(TsvdArgs<T> a, int npairs, int sweep) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= npairs) return;
+    PairHdr* h = reinterpret_cast<PairHdr*>(a.pairs + (size_t)f * a.pair_bytes);
+    if (!h->done && !h->rot[sweep & 1]) h->done = 1;
+    h->rot[sweep & 1] = 0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) tsvd_finish_kernel(TsvdArgs<T> a) {
+    __shared__ FinishSmem<T> sm;
+    const PairView<T> pv = pair_view(a, blockIdx.x);
+    pair_finish(a, pv, (T)pv.hdr->scale, pv.hdr->negl2, sm);
+}
+
 // S^ from sigma: S^1[f](i, i) = sigma[f][i], every other entry zero.
 template <typename T>
 __global__ void __launch_bounds__(256) tsvd_sigma_kernel(const T* __restrict__ sigma, T* __restrict__ Sh, int m, int n,
@@ -537,13 +747,41 @@ bool tsvd_dims_ok(int m, int n, int p) {
            (m > n ? m : n) <= kMaxMax;
 }
 
-// The pair kernel on a transformed A^: U^, V^ and sigma.
+// Staged units per block of the block sweeps for an m x n pair matrix (0:
+// the single-workgroup kernel serves this size).
+template <typename T>
+int tsvd_block_size(int m, int n) {
+    const int r = m > n ? m : n, c = m > n ? n : m;
+    const size_t unit = (size_t)(2 * r + 2 * c) * sizeof(typename Cx<T>::type);   // data + rotation column
+    int bs = (int)(kBlockLds / (2 * unit));
+    bs = bs < c ? bs : c;                 // at least two blocks
+    if (bs >= 8) bs &= ~7;                // one cross pair per wave and round
+    return (bs >= 4 && 2 * c >= kBlockMinUnits) ? bs : 0;
+}
+
+// The pair kernels on a transformed A^: U^, V^ and sigma.
 template <typename T>
 hipError_t launch_tsvd_pairs(int m, int n, int p, const T* Ah, int lda, T* Uh, int ldu, T* Vh, int ldv, T* sigma,
                              char* pairs, hipStream_t stream) {
     const size_t pb = pair_scratch_bytes<T>(m, n);
     TsvdArgs<T> args{Ah, Uh, Vh, sigma, pairs, pb, m, n, p, lda, ldu, ldv};
-    hipLaunchKernelGGL(tsvd_pair_kernel<T>, dim3(p / 2 + 1), dim3(kThreads), 0, stream, args);
+    const int npairs = p / 2 + 1;
+    const int bs = tsvd_block_size<T>(m, n);
+    if (!bs) {
+        hipLaunchKernelGGL(tsvd_pair_kernel<T>, dim3(npairs), dim3(kThreads), 0, stream, args);
+        return hipGetLastError();
+    }
+    const int c = m > n ? n : m;
+    const int nb = (2 * c + bs - 1) / bs, nbp = nb + (nb & 1);
+    hipLaunchKernelGGL(tsvd_prep_kernel<T>, dim3(npairs), dim3(kThreads), 0, stream, args);
+    for (int sweep = 0; sweep < kBlockMaxSweeps; ++sweep) {
+        for (int t = 0; t < nbp - 1; ++t)
+            hipLaunchKernelGGL(tsvd_round_kernel<T>, dim3(nbp / 2, npairs), dim3(kThreads), 0, stream, args, bs, t,
+                               sweep);
+        hipLaunchKernelGGL(tsvd_check_kernel<T>, dim3((npairs + 255) / 256), dim3(256), 0, stream, args, npairs,
+                           sweep);
+    }
+    hipLaunchKernelGGL(tsvd_finish_kernel<T>, dim3(npairs), dim3(kThreads), 0, stream, args);
     return hipGetLastError();
 }
 

@@ -75,6 +75,30 @@ def test_tsvd_against_oracle(prec, m, n, p):
     _check(A64, prec, *_run(A64, prec))
 
 
+# Shapes with 2 min(m, n) >= 128 run the block sweeps (many workgroups per
+# frequency pair, column blocks staged in LDS): ragged last blocks, an odd
+# number of blocks (an idle slot in the schedule), wide and tall, p = 1 and
+# p = 2 (quaternion pairs only) and odd p.
+BLOCK_SHAPES = [(100, 70, 5), (70, 100, 4), (64, 64, 2), (90, 90, 1), (130, 67, 3)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("m,n,p", BLOCK_SHAPES)
+def test_tsvd_block_sweeps_against_oracle(prec, m, n, p):
+    A64 = synth.quat_tensor(m, n, p, seed=8050 + 97 * m + 13 * n + p)
+    _check(A64, prec, *_run(A64, prec))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_tsvd_block_sweeps_rank_deficient(prec):
+    X = synth.quat_tensor(96, 20, 3, seed=8110)
+    Y = synth.quat_tensor(20, 80, 3, seed=8111)
+    A64 = oracle.tprod(X, Y)            # chi_f(A) has rank <= 40 < 160
+    U, S, V, sig = _run(A64, prec)
+    _check(A64, prec, U, S, V, sig)
+    assert np.all(sig[:, 20:] <= 10 * TOL[prec] * sig.max())
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_tsvd_rank_deficient_and_zero(prec):
     X = synth.quat_tensor(14, 3, 6, seed=8100)
