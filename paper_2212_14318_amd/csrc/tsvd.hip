@@ -63,6 +63,7 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+
 // Accumulator type of the inner products: double for both precisions, so
 // that the cosine between two FP32 columns is known far below the stopping
 // threshold (a float sum over 2 max(m, n) terms carries rounding errors of
@@ -109,6 +110,50 @@ __device__ __forceinline__ int circle(int q, int t, int nup) {
     return q == 0 ? 0 : ((q - 1 + t) % (nup - 1)) + 1;
 }
 
+// Sum over the 64 lanes of a wave (all lanes active), returned in every lane:
+// DPP adds within rows of 16 lanes (two quad permutations, the half-row and
+// row mirrors), the row broadcasts of lanes 15 and 31, and the total read
+// from lane 63.  Register moves only, no LDS round trips.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_shift(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_total(double v) {
+    v += dpp_shift<0xB1, 0xF>(v);      // quad_perm [1, 0, 3, 2]
+    v += dpp_shift<0x4E, 0xF>(v);      // quad_perm [2, 3, 0, 1]
+    v += dpp_shift<0x141, 0xF>(v);     // row_half_mirror
+    v += dpp_shift<0x140, 0xF>(v);     // row_mirror
+    v += dpp_shift<0x142, 0xA>(v);     // row_bcast:15 into rows 1 and 3
+    v += dpp_shift<0x143, 0xC>(v);     // row_bcast:31 into rows 2 and 3
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Parameters of a Jacobi step from the wave-summed inner products (gn =
+// |gamma| > 0): the phase e = gamma / |gamma| (applied as x_j conj(e)) and
+// the plane rotation (cs, sn) that then zeroes the real inner product, formed
+// in double and rounded once to T (one division).
+template <typename T, typename V>
+__device__ __forceinline__ void rotation(Acc al, Acc be, Acc g1r, Acc g1i, Acc g2r, Acc g2i, Acc gn, V& e1c,
+                                         V& e2c, T& cs, T& sn) {
+    const Acc ign = Acc(1) / gn;
+    e1c = V{T(g1r * ign), T(-g1i * ign)};
+    e2c = V{T(g2r * ign), T(-g2i * ign)};
+    const Acc zeta = (be - al) * (Acc(0.5) * ign);
+    const Acc az = fabs(zeta);
+    // |t| = 1 / (|zeta| + sqrt(1 + zeta^2)) = (sqrt(1 + zeta^2) - |zeta|)
+    const Acc w = sqrt(Acc(1) + az * az);
+    const Acc at = az > Acc(1) ? Acc(1) / (az + w) : w - az;
+    const Acc csd = Acc(1) / sqrt(Acc(1) + at * at);
+    cs = T(csd);
+    sn = T(csd * (zeta >= 0 ? at : -at));
+}
+
 // Partner component k of a quaternion column x of 2h entries.
 template <typename V>
 __device__ __forceinline__ V partner_at(const V* x, int k, int h) {
@@ -119,7 +164,7 @@ __device__ __forceinline__ V partner_at(const V* x, int k, int h) {
 // columns qi, qj (2hq entries), executed by one wave.  Returns true if a
 // rotation was applied.
 template <typename T, typename V>
-__device__ bool jacobi_pair(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool quat, T tol, Acc negl2, int lane) {
+__device__ __forceinline__ bool jacobi_pair(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool quat, T tol, Acc negl2, int lane) {
     Acc al = 0, be = 0, g1r = 0, g1i = 0, g2r = 0, g2i = 0;
     for (int k = lane; k < h; k += 64) {
         const V a0 = xi[k], a1 = xi[k + h], b0 = xj[k], b1 = xj[k + h];
@@ -135,13 +180,13 @@ __device__ bool jacobi_pair(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool quat
             g2i += (a0x * b1y + a0y * b1x) - (a1x * b0y + a1y * b0x);
         }
     }
-    al = wave_sum(al);
-    be = wave_sum(be);
-    g1r = wave_sum(g1r);
-    g1i = wave_sum(g1i);
+    al = wave_total(al);
+    be = wave_total(be);
+    g1r = wave_total(g1r);
+    g1i = wave_total(g1i);
     if (quat) {
-        g2r = wave_sum(g2r);
-        g2i = wave_sum(g2i);
+        g2r = wave_total(g2r);
+        g2i = wave_total(g2i);
     }
     // a column at rounding level of the whole matrix belongs to the null
     // space: rotating it only stirs rounding errors (and never converges)
@@ -150,11 +195,9 @@ __device__ bool jacobi_pair(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool quat
     if (!(gn > (Acc)tol * sqrt(al * be))) return false;
     // x_j <- x_j conj(e), e = gamma / |gamma| (a unit quaternion, or a complex
     // phase when g2 = 0): afterwards x_i^* x_j = |gamma| is real
-    const V e1c = V{T(g1r / gn), T(-g1i / gn)}, e2c = V{T(g2r / gn), T(-g2i / gn)};
-    const Acc zeta = (be - al) / (2 * gn);
-    const Acc t = (zeta >= 0 ? Acc(1) : Acc(-1)) / (fabs(zeta) + sqrt(Acc(1) + zeta * zeta));
-    const Acc csd = Acc(1) / sqrt(Acc(1) + t * t);
-    const T cs = T(csd), sn = T(csd * t);
+    V e1c, e2c;
+    T cs, sn;
+    rotation<T, V>(al, be, g1r, g1i, g2r, g2i, gn, e1c, e2c, cs, sn);
     auto apply = [&](V* ci, V* cj, int hh) {
         for (int k = lane; k < hh; k += 64) {
             const V a0 = ci[k], a1 = ci[k + hh], b0 = cj[k], b1 = cj[k + hh];
@@ -178,7 +221,7 @@ __device__ bool jacobi_pair(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool quat
 // products and the update (K loads per lane and column half issued together):
 // for h, hq <= 64 K.
 template <typename T, typename V, int K>
-__device__ bool jacobi_pair_reg(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool quat, T tol, Acc negl2, int lane) {
+__device__ __forceinline__ bool jacobi_pair_reg(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool quat, T tol, Acc negl2, int lane) {
     // the rotation columns are loaded with the data columns (one memory
     // round trip per pair); they are only written back if a rotation happens
     V a0[K], a1[K], b0[K], b1[K], c0[K], c1[K], d0[K], d1[K];
@@ -209,22 +252,20 @@ __device__ bool jacobi_pair_reg(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool 
             g2i += (a0x * b1y + a0y * b1x) - (a1x * b0y + a1y * b0x);
         }
     }
-    al = wave_sum(al);
-    be = wave_sum(be);
-    g1r = wave_sum(g1r);
-    g1i = wave_sum(g1i);
+    al = wave_total(al);
+    be = wave_total(be);
+    g1r = wave_total(g1r);
+    g1i = wave_total(g1i);
     if (quat) {
-        g2r = wave_sum(g2r);
-        g2i = wave_sum(g2i);
+        g2r = wave_total(g2r);
+        g2i = wave_total(g2i);
     }
     if (al <= negl2 || be <= negl2) return false;
     const Acc gn = sqrt(g1r * g1r + g1i * g1i + g2r * g2r + g2i * g2i);
     if (!(gn > (Acc)tol * sqrt(al * be))) return false;
-    const V e1c = V{T(g1r / gn), T(-g1i / gn)}, e2c = V{T(g2r / gn), T(-g2i / gn)};
-    const Acc zeta = (be - al) / (2 * gn);
-    const Acc tt = (zeta >= 0 ? Acc(1) : Acc(-1)) / (fabs(zeta) + sqrt(Acc(1) + zeta * zeta));
-    const Acc csd = Acc(1) / sqrt(Acc(1) + tt * tt);
-    const T cs = T(csd), sn = T(csd * tt);
+    V e1c, e2c;
+    T cs, sn;
+    rotation<T, V>(al, be, g1r, g1i, g2r, g2i, gn, e1c, e2c, cs, sn);
     auto rot = [&](V& u0, V& u1, V& w0, V& w1) {
         V r0 = cmul(e1c, w0), r1 = cmul(e1c, w1);
         if (quat) {
@@ -601,6 +642,22 @@ __global__ void __launch_bounds__(kThreads) tsvd_prep_kernel(TsvdArgs<T> a) {
     pair_prep(a, pv, s_red, scale, negl2);
 }
 
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// Copy bytes (a multiple of 16, both ends 16-byte aligned) from global memory
+// to LDS by DMA: global_load_lds_dwordx4 moves 64 x 16 B per wave
+// instruction into 1 KB of LDS (lane L at byte 16 L), without registers;
+// lanes past the end are masked off.  The caller waits (s_waitcnt, barrier).
+template <typename V>
+__device__ __forceinline__ void dma_copy(const V* src, V* dst, size_t bytes, int wave, int lane) {
+    const char* s = reinterpret_cast<const char*>(src);
+    char* d = reinterpret_cast<char*>(dst);
+    for (size_t off = (size_t)wave * 1024; off < bytes; off += (size_t)kWaves * 1024) {
+        const size_t mine = off + 16 * (size_t)lane;
+        if (mine < bytes) __builtin_amdgcn_global_load_lds((const void*)(s + mine), (lds_void_t*)(d + off), 16, 0, 0);
+    }
+}
+
 // grid: (block pairs of the longest schedule, frequency pairs)
 template <typename T>
 __global__ void __launch_bounds__(kThreads) tsvd_round_kernel(TsvdArgs<T> a, int bs, int t, int sweep) {
@@ -620,17 +677,23 @@ __global__ void __launch_bounds__(kThreads) tsvd_round_kernel(TsvdArgs<T> a, int
     const int R = pv.R, Rq = pv.Rq, nk = nI + nJ;
     V* xs = reinterpret_cast<V*>(s_cols);            // staged unit k: xs + k R, qs + k Rq
     V* qs = xs + (size_t)nk * R;
-    auto unit = [&](int k) { return k < nI ? I * bs + k : J * bs + (k - nI); };
-    for (int e = tid; e < nk * R; e += kThreads) xs[e] = pv.X[(size_t)unit(e / R) * R + e % R];
-    for (int e = tid; e < nk * Rq; e += kThreads) qs[e] = pv.Q[(size_t)unit(e / Rq) * Rq + e % Rq];
+    // each block's columns are contiguous in X and in Q: four DMA copies
+    dma_copy(pv.X + (size_t)I * bs * R, xs, (size_t)nI * R * sizeof(V), wave, lane);
+    dma_copy(pv.X + (size_t)J * bs * R, xs + (size_t)nI * R, (size_t)nJ * R * sizeof(V), wave, lane);
+    dma_copy(pv.Q + (size_t)I * bs * Rq, qs, (size_t)nI * Rq * sizeof(V), wave, lane);
+    dma_copy(pv.Q + (size_t)J * bs * Rq, qs + (size_t)nI * Rq, (size_t)nJ * Rq * sizeof(V), wave, lane);
+    __builtin_amdgcn_s_waitcnt(0);                   // this wave's copies have landed
     if (tid == 0) s_rot = 0;
     __syncthreads();
     const T tol = jacobi_tol<T>(R);
     const Acc negl2 = pv.hdr->negl2;
     bool rot = false;
+    const int r = pv.r, c = pv.c;
     auto step = [&](int i, int j) {
-        rot |= jacobi_pair<T, V>(xs + (size_t)i * R, xs + (size_t)j * R, qs + (size_t)i * Rq,
-                                 qs + (size_t)j * Rq, pv.r, pv.c, pv.quat, tol, negl2, lane);
+        V *xi = xs + (size_t)i * R, *xj = xs + (size_t)j * R, *qi = qs + (size_t)i * Rq, *qj = qs + (size_t)j * Rq;
+        rot |= (r <= 64 && c <= 64)     ? jacobi_pair_reg<T, V, 1>(xi, xj, qi, qj, r, c, pv.quat, tol, negl2, lane)
+               : (r <= 256 && c <= 256) ? jacobi_pair_reg<T, V, 4>(xi, xj, qi, qj, r, c, pv.quat, tol, negl2, lane)
+                                        : jacobi_pair<T, V>(xi, xj, qi, qj, r, c, pv.quat, tol, negl2, lane);
     };
     if (t == 0) {
         // pairs within block I (staged 0 .. nI - 1) and within block J
@@ -673,8 +736,31 @@ __global__ void __launch_bounds__(kThreads) tsvd_round_kernel(TsvdArgs<T> a, int
     if (rot && lane == 0) s_rot = 1;
     __syncthreads();
     if (!s_rot) return;
-    for (int e = tid; e < nk * R; e += kThreads) pv.X[(size_t)unit(e / R) * R + e % R] = xs[e];
-    for (int e = tid; e < nk * Rq; e += kThreads) pv.Q[(size_t)unit(e / Rq) * Rq + e % Rq] = qs[e];
+    // write back the four contiguous ranges in 16-byte words, four LDS reads
+    // in flight per thread before the stores
+    auto copy_out = [&](V* g, const V* sh, size_t bytes) {
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        u4* gd = reinterpret_cast<u4*>(g);
+        const u4* sd = reinterpret_cast<const u4*>(sh);
+        const size_t n16 = bytes / 16;
+        for (size_t i = tid; i < n16; i += 4 * kThreads) {
+            u4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const size_t j = i + (size_t)u * kThreads;
+                v[u] = j < n16 ? sd[j] : u4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const size_t j = i + (size_t)u * kThreads;
+                if (j < n16) gd[j] = v[u];
+            }
+        }
+    };
+    copy_out(pv.X + (size_t)I * bs * R, xs, (size_t)nI * R * sizeof(V));
+    copy_out(pv.X + (size_t)J * bs * R, xs + (size_t)nI * R, (size_t)nJ * R * sizeof(V));
+    copy_out(pv.Q + (size_t)I * bs * Rq, qs, (size_t)nI * Rq * sizeof(V));
+    copy_out(pv.Q + (size_t)J * bs * Rq, qs + (size_t)nI * Rq, (size_t)nJ * Rq * sizeof(V));
     if (tid == 0) pv.hdr->rot[sweep & 1] = 1;
 }
 
