@@ -544,7 +544,7 @@ def svd_flops(rows, cols):
 
 
 def tsvd_flops(m, n, p):
-    """Algorithmic work of the t-SVD's pair kernel: one complex SVD of the
+    """Algorithmic work of the t-SVD's Fourier-domain stage: one complex SVD of the
     2 max(m,n) x 2 min(m,n) matrix chi_f(A) per pair {f, -f} with f != -f, and
     half of that for each self-paired frequency (a quaternion SVD of half the
     size: an eighth of the elements at four times the operations each)."""
@@ -555,11 +555,12 @@ def tsvd_flops(m, n, p):
 
 
 def bench_tsvd(args, wl, dev, stream):
-    """t-SVD workload: one step = qt_tsvd (tube FFT, pair kernel, S^ fill,
-    inverse FFTs of U^, V^, S^).  The pair kernel is timed on its own through
+    """t-SVD workload: one step = qt_tsvd (tube FFT, Jacobi sweeps per
+    frequency pair, S^ fill, inverse FFTs of U^, V^, S^).  The Fourier-domain
+    stage (preparation, block-sweep rounds, finish) is timed on its own through
     qt_fourier_tsvd on the transformed input; its roofline is the FP32 vector
-    ALU (the Jacobi sweeps are column updates in VALU with the columns held in
-    L2), reported against the SVD operation count."""
+    ALU (the Jacobi sweeps are column updates in VALU on columns staged in
+    LDS), reported against the SVD operation count."""
     import numpy as np
     import torch
 
@@ -626,7 +627,7 @@ def bench_tsvd(args, wl, dev, stream):
         res[prec] = {"ms_per_step": times["whole"], "pair_kernel_ms": times["pairs"],
                      "pair_kernel_tflops": F / (times["pairs"] * 1e-3) / 1e12,
                      "sigma_max_rel_err": err, "stage_equals_qt_tsvd": same, "steps": steps}
-        log(f"[bench] tsvd {prec}: {times['whole']:.3f} ms per qt_tsvd, pair kernel {times['pairs']:.3f} ms "
+        log(f"[bench] tsvd {prec}: {times['whole']:.3f} ms per qt_tsvd, Fourier-domain stage {times['pairs']:.3f} ms "
             f"({res[prec]['pair_kernel_tflops']:.3f} TFLOP/s of SVD work), sigma err {err:.2e}")
     head = precs[0]
     r = res[head]
@@ -650,7 +651,7 @@ def bench_tsvd(args, wl, dev, stream):
             "config": {"workload": wl["desc"], "precision": head, "svd_flops_per_step": F},
             "roofline": {"bound": "alu", "achieved": round(r["pair_kernel_tflops"], 4), "peak": peak,
                          "unit": "TFLOP/s", "frac": round(r["pair_kernel_tflops"] / peak, 5), "traffic": None,
-                         "kernel": "tsvd_pair_kernel (qt_fourier_tsvd)"},
+                         "kernel": "t-SVD Fourier-domain stage (qt_fourier_tsvd: prep, block-sweep rounds, finish)"},
             "per_precision": res, "cpu_baseline": cpu}
 
 
