@@ -23,14 +23,23 @@ namespace {
 using namespace detail;
 
 // Persistent product kernel of one tile shape: the grid strides its own
-// item list (all items of the launch have tile shape CFG).
+// item list (all items of the launch have tile shape CFG).  Workgroups are
+// dispatched to the 8 XCDs in turn (workgroup w on XCD w % 8), so in each
+// stride the workgroups of one XCD take a run of consecutive items: the tiles
+// of one (problem, frequency), adjacent in the list, then share that XCD's L2
+// for their A rows and B columns instead of each fetching them from beyond it.
+constexpr int kXcds = 8;
+
 template <int PREC, int CFG>
 __global__ void __launch_bounds__(64 * tile_waves(PREC, CFG))
 batched_gemm_kernel(const BatchGemmProb* __restrict__ probs, const BatchGemmItem* __restrict__ items,
                     int nitems) {
     constexpr int MT = tile_mt(CFG), NT = tile_nt(CFG);
     __shared__ __attribute__((aligned(16))) V2Smem<MT, NT> sm;
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int grid = gridDim.x;
+    const int slot = grid % kXcds == 0 ? (blockIdx.x % kXcds) * (grid / kXcds) + blockIdx.x / kXcds
+                                       : blockIdx.x;
+    for (int it = slot; it < nitems; it += grid) {
         const BatchGemmItem item = items[it];
         const BatchGemmProb pr = probs[item.prob];
         tile_v2<PREC, MT, NT, tile_waves(PREC, CFG), plane_groups(PREC, CFG)>(pr.a, item.f, item.tm * MT,
