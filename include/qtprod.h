@@ -87,12 +87,11 @@ typedef enum {
     QT_SPLIT_FP16 = 2,  /* as QT_SPLIT_BF16 with fp16 hi+lo; operands scaled by a
                            power of two per frequency (A^[f]) and per frequency
                            pair (B^[f], B^[-f]) computed on the device.  Served
-                           by qt_tprod, qt_tprod_noalloc and qt_tprod_backward
-                           (each product computes the scales of its own
-                           operands); qt_fourier_tprod (its operands are the
-                           caller's), qt_tprod_batched / qt_batched_plan_create,
-                           qt_tprod_complex and qt_tprod_real return
-                           QT_ERR_UNSUPPORTED for it */
+                           by qt_tprod, qt_tprod_noalloc, qt_tprod_backward and
+                           the batched calls (each product computes the scales
+                           of its own operands); qt_fourier_tprod (its operands
+                           are the caller's), qt_tprod_complex and
+                           qt_tprod_real return QT_ERR_UNSUPPORTED for it */
     QT_FP64 = 3,        /* every step in double (small problems, validation) */
     QT_PRECISION_INT_RANGE = 0x7fffffff  /* not a precision: full int range (checked values
                                             outside 0..3 are rejected, not undefined) */
@@ -203,8 +202,13 @@ size_t qt_batched_workspace_size(int count, const qt_problem* probs, qt_precisio
  * memory, so the call returns once it is staged.
  * probs is a HOST array read before the call returns.  Each problem obeys the
  * single-call preconditions; outputs must not overlap any input or output.
- * precision: QT_FP32 or QT_SPLIT_BF16; any p <= QT_MAX_P (problems whose p
- * is not 7-smooth or exceeds 64 get tube-FFT launches of their own).
+ * precision: QT_FP32, QT_SPLIT_BF16 or QT_SPLIT_FP16 (QT_FP64 returns
+ * QT_ERR_UNSUPPORTED); any p <= QT_MAX_P (problems whose p is not 7-smooth or
+ * exceeds 64 get tube-FFT launches of their own).  QT_SPLIT_FP16 adds three
+ * launches between the phases: the largest magnitude of every face of every
+ * A_i^, B_i^, each problem's power-of-two scales (A_i^ per frequency, B_i^ per
+ * pair {f, -f}, as qt_tprod computes them), and the scaled fp16 words written
+ * over the Fourier operands in the workspace.
  * The first call per device and precision runs the autotuner (allocates and
  * synchronises once).  Same arithmetic as qt_tprod per problem (tile shapes
  * may differ, hence rounding order).  For graph replays use the plan API. */
@@ -262,7 +266,9 @@ qt_status qt_batched_plan_destroy(qt_batched_plan plan);
  * model t = alpha + beta * ceil(n / 16), and times both radix orders of the
  * batched tube FFT for every batched p.  Allocates scratch memory and
  * synchronises `stream`.  Single-problem calls then use the cost model for
- * their tile shape too. */
+ * their tile shape too.  precision: QT_FP32, QT_SPLIT_BF16 or QT_SPLIT_FP16
+ * (the split-fp16 tiles share the split-bf16 cost model: same instruction
+ * mix at the same rate); QT_FP64 returns QT_ERR_UNSUPPORTED. */
 qt_status qt_autotune(qt_precision precision, hipStream_t stream);
 
 /* Workspace bytes needed by qt_tprod_complex (0 if an argument is invalid or

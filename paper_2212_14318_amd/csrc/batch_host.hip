@@ -48,7 +48,12 @@ int current_device() {
     return hipGetDevice(&d) == hipSuccess ? d : -1;
 }
 
+// The split-fp16 tiles run the same instruction mix as the split-bf16 ones
+// (f16 instead of bf16 MFMA, same rate), so they share its cost model.
+int tune_precision(int prec) { return prec == QT_SPLIT_FP16 ? QT_SPLIT_BF16 : prec; }
+
 bool tuned(int prec, TuneTable* out) {
+    prec = tune_precision(prec);
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     auto it = g_tune.find({current_device(), prec});
     if (it == g_tune.end() || !it->second.done) return false;
@@ -240,6 +245,7 @@ int run_tuner(int prec, hipStream_t stream, TuneTable* out) {
 }
 
 int ensure_tuned(int prec, hipStream_t stream, TuneTable* out) {
+    prec = tune_precision(prec);
     if (tuned(prec, out)) return QT_OK;
     TuneTable t;
     const int st = run_tuner(prec, stream, &t);
@@ -272,16 +278,17 @@ bool problem_ok(const qt_problem& q) {
 
 // ------------------------------------------------------- work-list layout
 struct DescLayout {
-    size_t fwd_jobs, fwd_items, probs, gitems, inv_jobs, inv_items, tensors, total;
-    long n_fwd_items_max, n_gitems_max, n_inv_items_max;
+    size_t fwd_jobs, fwd_items, probs, gitems, inv_jobs, inv_items, h_jobs, h_items, h_floats, tensors, total;
+    long n_fwd_items_max, n_gitems_max, n_inv_items_max, n_h_items;
 };
 
 DescLayout desc_layout(int count, const qt_problem* probs) {
     DescLayout L{};
-    long nfi = 0, ngi = 0, nii = 0;
+    long nfi = 0, ngi = 0, nii = 0, nfaces = 0;
     size_t tens = 0;
     for (int i = 0; i < count; ++i) {
         const qt_problem& q = probs[i];
+        nfaces += 2L * q.p;                                     // split fp16: faces of A^ and B^
         nfi += 2 * (((long)q.m * q.n + 255) / 256) + 2 * (((long)q.n * q.s + 255) / 256);
         ngi += (long)q.p * ((q.m + 31) / 32) * ((q.s + 63) / 64);   // 32 x 64 is the smallest tile
         nii += 2 * (((long)q.m * q.s + 255) / 256);
@@ -295,11 +302,16 @@ DescLayout desc_layout(int count, const qt_problem* probs) {
     L.gitems = take(sizeof(BatchGemmItem) * ngi);
     L.inv_jobs = take(sizeof(BatchFftJob) * count);
     L.inv_items = take(sizeof(BatchFftItem) * nii);
+    // split fp16: operand jobs, face items, and per face a maximum and a scale
+    L.h_jobs = take(sizeof(BatchFp16Job) * 2 * count);
+    L.h_items = take(sizeof(BatchFp16Item) * nfaces);
+    L.h_floats = take(sizeof(float) * 2 * nfaces);
     L.tensors = off;
     L.total = off + tens;
     L.n_fwd_items_max = nfi;
     L.n_gitems_max = ngi;
     L.n_inv_items_max = nii;
+    L.n_h_items = nfaces;
     return L;
 }
 
@@ -325,6 +337,8 @@ struct HostLists {
     std::vector<FftBucket> fwd_buckets, inv_buckets;
     std::vector<BatchGemmProb> probs;
     std::vector<BatchGemmItem> gitems;      // grouped by tile shape, longest first in each group
+    std::vector<BatchFp16Job> h_jobs;       // split fp16 only: A^, B^ of every problem
+    std::vector<BatchFp16Item> h_items;
     int gfirst[detail::NUM_TILE_CFGS] = {}, gcount[detail::NUM_TILE_CFGS] = {};
 };
 
@@ -338,6 +352,7 @@ void add_fft_items(std::vector<BatchFftItem>& items, int job, long positions) {
 int build_lists(int count, const qt_problem* probs, int prec, char* ws, const DescLayout& L,
                 const TuneTable& tune, hipStream_t stream, HostLists* H) {
     size_t off = L.tensors;
+    long hface = 0;                          // split fp16: faces placed so far (2 p per problem)
     for (int i = 0; i < count; ++i) {
         const qt_problem& q = probs[i];
         Twiddles tw;
@@ -360,8 +375,21 @@ int build_lists(int count, const qt_problem* probs, int prec, char* ws, const De
         H->fwd_jobs.push_back(BatchFftJob{(const float*)q.B, Bh, tw.f32, q.n, q.s, q.s, ldb, q.p, pol, pack, 0});
         H->inv_jobs.push_back(BatchFftJob{Ch, (float*)q.C, tw.f32, q.m, q.s, ldc, q.s, q.p, pol, 0, 0});
         const int cfg = pick_tile(&tune, q.m, q.n, q.s);
+        const float* scales = nullptr;
+        if (prec == QT_SPLIT_FP16) {
+            // faces of A^ then of B^: a maximum each, then the scales (A^ at f,
+            // the B^ pair {f, -f}) in the same order
+            float* fmax = reinterpret_cast<float*>(ws + L.h_floats) + 2 * hface;
+            float* sc = fmax + 2 * q.p;
+            H->h_jobs.push_back(BatchFp16Job{Ah, fmax, sc, q.m, q.n, lda, q.p});
+            H->h_jobs.push_back(BatchFp16Job{Bh, fmax + q.p, sc + q.p, q.n, q.s, ldb, q.p});
+            for (int part = 0; part < 2; ++part)
+                for (int f = 0; f < q.p; ++f) H->h_items.push_back(BatchFp16Item{2 * i + part, f});
+            hface += 2 * q.p;
+            scales = sc;
+        }
         H->probs.push_back(BatchGemmProb{FacewiseArgs<float>{Ah, Bh, Ch, q.m, q.n, q.s, q.p, lda, ldb, ldc},
-                                         cfg, 0, 0, 0});
+                                         scales, cfg, 0});
     }
     // batched FFT items only for the lengths the batched kernel has
     for (int j = 0; j < (int)H->fwd_jobs.size(); ++j)
@@ -406,20 +434,23 @@ int build_lists(int count, const qt_problem* probs, int prec, char* ws, const De
         H->gcount[cfg] = (int)H->gitems.size() - H->gfirst[cfg];
     }
     if ((long)H->fwd_items.size() > L.n_fwd_items_max || (long)H->gitems.size() > L.n_gitems_max ||
-        (long)H->inv_items.size() > L.n_inv_items_max)
+        (long)H->inv_items.size() > L.n_inv_items_max || (long)H->h_items.size() > L.n_h_items ||
+        (long)H->h_jobs.size() > 2L * count)
         return QT_ERR_INVALID_ARG;   // cannot happen: the layout is an upper bound
     return QT_OK;
 }
 
 int upload(const HostLists& H, char* ws, const DescLayout& L, hipStream_t stream) {
     struct Part { size_t off; const void* src; size_t bytes; };
-    const Part parts[6] = {
+    const Part parts[8] = {
         {L.fwd_jobs, H.fwd_jobs.data(), H.fwd_jobs.size() * sizeof(BatchFftJob)},
         {L.fwd_items, H.fwd_items.data(), H.fwd_items.size() * sizeof(BatchFftItem)},
         {L.probs, H.probs.data(), H.probs.size() * sizeof(BatchGemmProb)},
         {L.gitems, H.gitems.data(), H.gitems.size() * sizeof(BatchGemmItem)},
         {L.inv_jobs, H.inv_jobs.data(), H.inv_jobs.size() * sizeof(BatchFftJob)},
         {L.inv_items, H.inv_items.data(), H.inv_items.size() * sizeof(BatchFftItem)},
+        {L.h_jobs, H.h_jobs.data(), H.h_jobs.size() * sizeof(BatchFp16Job)},
+        {L.h_items, H.h_items.data(), H.h_items.size() * sizeof(BatchFp16Item)},
     };
     for (const Part& pt : parts) {
         if (!pt.bytes) continue;
@@ -451,6 +482,11 @@ int enqueue(const HostLists& H, char* ws, const DescLayout& L, int prec, hipStre
             return QT_ERR_HIP;
     for (const SingleFft& sf : H.single)
         if (launch_tube_fft<float>(sf.p, false, sf.fwd, 2, sf.tw, stream) != hipSuccess) return QT_ERR_HIP;
+    if (!H.h_items.empty() &&
+        launch_batched_fp16_prep(reinterpret_cast<const BatchFp16Job*>(ws + L.h_jobs),
+                                 reinterpret_cast<const BatchFp16Item*>(ws + L.h_items), (int)H.h_items.size(), pj,
+                                 (int)H.probs.size(), stream) != hipSuccess)
+        return QT_ERR_HIP;
     for (int cfg = 0; cfg < detail::NUM_TILE_CFGS; ++cfg) {
         const int n = H.gcount[cfg];
         if (n && launch_batched_gemm(prec, cfg, pj, gi + H.gfirst[cfg], n, std::min(n, gemm_grid(prec, cfg)),
@@ -503,7 +539,7 @@ int validate(int count, const qt_problem* probs, int prec, void* ws, size_t ws_b
             }
         }
     }
-    if (prec != QT_FP32 && prec != QT_SPLIT_BF16) return QT_ERR_UNSUPPORTED;
+    if (prec == QT_FP64) return QT_ERR_UNSUPPORTED;
     for (int i = 0; i < count; ++i)
         if (probs[i].p > QT_MAX_P) return QT_ERR_UNSUPPORTED;
     return QT_OK;
@@ -546,7 +582,8 @@ struct qt_batched_plan_s {
 extern "C" {
 
 qt_status qt_autotune(qt_precision precision, hipStream_t stream) {
-    if (precision != QT_FP32 && precision != QT_SPLIT_BF16) return QT_ERR_UNSUPPORTED;
+    if (precision != QT_FP32 && precision != QT_SPLIT_BF16 && precision != QT_SPLIT_FP16)
+        return QT_ERR_UNSUPPORTED;
     qt::TuneTable t;
     return qt::to_status(qt::ensure_tuned(precision, stream, &t));
 }

@@ -349,17 +349,6 @@ absmax_partial_kernel(const float* __restrict__ X, int rows, int cols, int ld, i
     if (threadIdx.x == 0) partial[(size_t)f * nblk + blockIdx.x] = red[0];
 }
 
-__device__ __forceinline__ float pow2_scale(float mx) {
-    if (!(mx > 0.f) || !isfinite(mx)) return 1.f;
-    int e;
-    (void)frexpf(mx, &e);                 // mx < 2^e, e in [-148, 128]
-    // mx * scale < 2^15; the exponent is capped at 126 so that the scale and
-    // its reciprocal are normal floats (only inputs below 2^-111 hit the cap,
-    // and they then land below 2^15 instead of in [2^14, 2^15))
-    const int k = 15 - e < 126 ? 15 - e : 126;
-    return ldexpf(1.f, k);
-}
-
 __global__ void fp16_scales_kernel(const float* __restrict__ pa, int nba, const float* __restrict__ pb,
                                    int nbb, int p, float* __restrict__ scales) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;

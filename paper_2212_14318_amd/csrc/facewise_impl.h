@@ -103,6 +103,19 @@ __device__ __forceinline__ V8 neg8(V8 x) {
     return __builtin_bit_cast(V8, b);
 }
 
+// Power-of-two scale of a split-fp16 operand block whose largest magnitude
+// is mx: mx * scale < 2^15 (the hi halves stay below the fp16 maximum with
+// room for the products' sums).  The exponent is capped at 126 so that the
+// scale and its reciprocal are normal floats (only inputs below 2^-111 hit
+// the cap, and they then land below 2^15 instead of in [2^14, 2^15)).
+__device__ __forceinline__ float pow2_scale(float mx) {
+    if (!(mx > 0.f) || !isfinite(mx)) return 1.f;
+    int e;
+    (void)frexpf(mx, &e);                 // mx < 2^e, e in [-148, 128]
+    const int k = 15 - e < 126 ? 15 - e : 126;
+    return ldexpf(1.f, k);
+}
+
 // Tile shapes (MT x NT) compiled for both kernels; the id is what the
 // autotuner stores and what a batched work item carries.
 // 32x64 cuts the row padding of small problems (m <= 32, or m just above a

@@ -151,6 +151,16 @@ __device__ __forceinline__ unsigned split_bf16_word(float x) {
            ((unsigned)__builtin_bit_cast(unsigned short, lo) << 16);
 }
 
+// fp16 split of one real scaled by a power of two sc (exact): low half
+// hi = rn_fp16(x sc), high half lo = rn_fp16(x sc - hi).
+__device__ __forceinline__ unsigned split_fp16_word(float x, float sc) {
+    const float y = x * sc;
+    const _Float16 hi = (_Float16)y;
+    const _Float16 lo = (_Float16)(y - (float)hi);
+    return (unsigned)__builtin_bit_cast(unsigned short, hi) |
+           ((unsigned)__builtin_bit_cast(unsigned short, lo) << 16);
+}
+
 // Real tubes (the DFT of a real sequence is Hermitian, X^[p - f] =
 // conj(X^[f])): forward from one real plane to faces 0..p/2 of the (Re, Im)
 // planes, inverse from those faces back to the real plane.  sre / dre point

@@ -49,13 +49,7 @@ fp16_words_kernel(float* __restrict__ X, long p, long rows, long cols, long ld, 
         const float sc = scale[(fr / rows) % p];
         float* row = X + fr * ld + 4 * g;
         const int n = (int)(cols - 4 * g < 4 ? cols - 4 * g : 4);
-        auto word = [sc](float x) {
-            const float y = x * sc;
-            const _Float16 hi = (_Float16)y;
-            const _Float16 lo = (_Float16)(y - (float)hi);
-            return (unsigned)__builtin_bit_cast(unsigned short, hi) |
-                   ((unsigned)__builtin_bit_cast(unsigned short, lo) << 16);
-        };
+        auto word = [sc](float x) { return detail::split_fp16_word(x, sc); };
         if (n == 4) {
             const float4 v = *reinterpret_cast<const float4*>(row);
             *reinterpret_cast<uint4*>(row) = uint4{word(v.x), word(v.y), word(v.z), word(v.w)};

@@ -12,7 +12,7 @@ from gpu_util import rel_err, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
-TOLS = {"fp32": 1e-5, "split_bf16": 5e-5}
+TOLS = {"fp32": 1e-5, "split_bf16": 5e-5, "split_fp16": 5e-5}
 P_SET = [1, 2, 3, 5, 7, 8, 12, 16, 30, 32, 45, 64]
 
 
@@ -27,12 +27,12 @@ def small_batch(count, seed, lo=1, hi=150):
     return out
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
 def test_autotune_runs(prec):
     autotune(prec)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
 def test_batched_matches_oracle(prec):
     batch = small_batch(24, seed=11)
     As = [to_dev(A) for A, _ in batch]
@@ -47,6 +47,33 @@ def test_batched_matches_oracle(prec):
     assert worst <= TOLS[prec]
 
 
+def test_batched_fp16_face_scales():
+    """Split fp16 with faces scaled over 1e-3 .. 1e3 (and one problem of tiny
+    magnitude): the per-frequency scales of every problem keep each Fourier
+    face in fp16 range, as in the single-problem path."""
+    batch = small_batch(12, seed=17, lo=4, hi=100)
+    rng = np.random.Generator(np.random.PCG64(170))
+    scaled = []
+    for i, (A, B) in enumerate(batch):
+        p = A.shape[1]
+        fa = 10.0 ** rng.uniform(-3, 3, p)
+        fb = 10.0 ** rng.uniform(-3, 3, p)
+        A = A * fa[None, :, None, None]
+        B = B * fb[None, :, None, None]
+        if i == 0:
+            A = A * 1e-20
+        scaled.append((A, B))
+    As = [to_dev(A) for A, _ in scaled]
+    Bs = [to_dev(B) for _, B in scaled]
+    Cs = tprod_batched(As, Bs, "split_fp16")
+    torch.cuda.synchronize()
+    worst = 0.0
+    for (A, B), C in zip(scaled, Cs):
+        worst = max(worst, rel_err(to_np(C), oracle.tprod_faces(A, B)))
+    print(f"split_fp16 batched, face scales 1e-3..1e3: worst rel err {worst:.3e}")
+    assert worst <= TOLS["split_fp16"]
+
+
 def test_batched_matches_single_calls():
     batch = small_batch(10, seed=12, lo=20, hi=200)
     As = [to_dev(A) for A, _ in batch]
@@ -57,7 +84,7 @@ def test_batched_matches_single_calls():
         assert rel_err(to_np(C), to_np(ref)) <= 2e-6
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
 def test_batched_any_p(prec):
     """Lengths without a batched FFT kernel (primes, p > 64, Bluestein and
     register single-problem transforms) mixed with batched ones, in one call
@@ -87,7 +114,7 @@ def test_batched_any_p(prec):
         plan.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
 def test_plan_replays_track_inputs(prec):
     """Replay the captured graph several times with eager work and syncs in
     between; every replay must equal the eager single-call results."""
@@ -110,7 +137,7 @@ def test_plan_replays_track_inputs(prec):
         plan.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
 def test_c4_full_batch(prec):
     """The 512-problem batch: 48 entries of every problem (computed one by one
     from the definition), each problem held to the stated tolerance."""
