@@ -87,11 +87,11 @@ typedef enum {
     QT_SPLIT_FP16 = 2,  /* as QT_SPLIT_BF16 with fp16 hi+lo; operands scaled by a
                            power of two per frequency (A^[f]) and per frequency
                            pair (B^[f], B^[-f]) computed on the device.  Served
-                           by qt_tprod, qt_tprod_noalloc, qt_tprod_backward and
-                           the batched calls (each product computes the scales
-                           of its own operands); qt_fourier_tprod (its operands
-                           are the caller's), qt_tprod_complex and
-                           qt_tprod_real return QT_ERR_UNSUPPORTED for it */
+                           by qt_tprod, qt_tprod_noalloc, qt_tprod_backward,
+                           the batched calls, qt_tprod_complex and
+                           qt_tprod_real (each product computes the scales of
+                           its own operands); qt_fourier_tprod (its operands
+                           are the caller's) returns QT_ERR_UNSUPPORTED */
     QT_FP64 = 3,        /* every step in double (small problems, validation) */
     QT_PRECISION_INT_RANGE = 0x7fffffff  /* not a precision: full int range (checked values
                                             outside 0..3 are rejected, not undefined) */
@@ -272,7 +272,7 @@ qt_status qt_batched_plan_destroy(qt_batched_plan plan);
 qt_status qt_autotune(qt_precision precision, hipStream_t stream);
 
 /* Workspace bytes needed by qt_tprod_complex (0 if an argument is invalid or
- * the precision is not QT_FP32 / QT_SPLIT_BF16). */
+ * the precision is QT_FP64). */
 size_t qt_complex_workspace_size(int m, int n, int s, int p, qt_precision precision);
 
 /* T-product of complex tensors, the special case A2 = B2 = 0 of the
@@ -282,15 +282,17 @@ size_t qt_complex_workspace_size(int m, int n, int s, int p, qt_precision precis
  * instead of four coupled ones, and one complex tube FFT per tensor.  Layout:
  * TWO planes per tensor, [2][p][rows][cols] = (Re, Im); A: m x n x p,
  * B: n x s x p, C: m x s x p (device pointers, C fully overwritten).
- * precision: QT_FP32 (FP32 MFMA) or QT_SPLIT_BF16 (bf16 hi+lo products, as
- * for qt_tprod); QT_SPLIT_FP16 and QT_FP64 return QT_ERR_UNSUPPORTED.  A real
- * tensor is a complex one with a zero imaginary plane.  Same preconditions,
- * ownership and error behaviour as qt_tprod. */
+ * precision: QT_FP32 (FP32 MFMA), QT_SPLIT_BF16 (bf16 hi+lo products, as
+ * for qt_tprod) or QT_SPLIT_FP16 (fp16 hi+lo with a power-of-two scale per
+ * frequency for A^[f] and for B^[f], there being no -f coupling); QT_FP64
+ * returns QT_ERR_UNSUPPORTED.  A real tensor is a complex one with a zero
+ * imaginary plane.  Same preconditions, ownership and error behaviour as
+ * qt_tprod. */
 qt_status qt_tprod_complex(int m, int n, int s, int p, const void* A, const void* B, void* C,
                      qt_precision precision, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Workspace bytes needed by qt_tprod_real (0 if an argument is invalid or the
- * precision is not QT_FP32 / QT_SPLIT_BF16). */
+ * precision is QT_FP64). */
 size_t qt_real_workspace_size(int m, int n, int s, int p, qt_precision precision);
 
 /* T-product of real tensors (Algorithm 2.1 of the paper on real input, the
@@ -299,9 +301,10 @@ size_t qt_real_workspace_size(int m, int n, int s, int p, qt_precision precision
  * multiplied (one complex product C^[f] = A^[f] B^[f] each) and inverted:
  * p/2 + 1 complex products instead of p.  Layout: ONE plane per tensor,
  * [p][rows][cols] row-major faces; A: m x n x p, B: n x s x p, C: m x s x p
- * (device pointers, C fully overwritten).  precision: QT_FP32 or
- * QT_SPLIT_BF16; QT_SPLIT_FP16 and QT_FP64 return QT_ERR_UNSUPPORTED.  Same
- * preconditions, ownership and error behaviour as qt_tprod. */
+ * (device pointers, C fully overwritten).  precision: QT_FP32, QT_SPLIT_BF16
+ * or QT_SPLIT_FP16 (as for qt_tprod_complex, on the p/2 + 1 faces); QT_FP64
+ * returns QT_ERR_UNSUPPORTED.  Same preconditions, ownership and error
+ * behaviour as qt_tprod. */
 qt_status qt_tprod_real(int m, int n, int s, int p, const void* A, const void* B, void* C,
                   qt_precision precision, void* ws, size_t ws_bytes, hipStream_t stream);
 

@@ -483,22 +483,26 @@ namespace {
 int cx_faces(int p, bool real) { return real ? p / 2 + 1 : p; }
 
 size_t cx_workspace(int m, int n, int s, int p, qt_precision precision, bool real) {
-    if ((precision != QT_FP32 && precision != QT_SPLIT_BF16) || !dims_ok(m, n, p) || !dims_ok(n, s, p) ||
-        !dims_ok(m, s, p))
+    if ((precision != QT_FP32 && precision != QT_SPLIT_BF16 && precision != QT_SPLIT_FP16) || !dims_ok(m, n, p) ||
+        !dims_ok(n, s, p) || !dims_ok(m, s, p))
         return 0;
     const long h = cx_faces(p, real);
     // two planes (Re, Im) of h faces per tensor
     auto part = [h](long rows, long cols) {
         return align_up(2 * (size_t)h * (size_t)rows * (size_t)qt::fourier_ld(cols) * sizeof(float));
     };
-    return part(m, n) + part(n, s) + part(m, s);
+    size_t total = part(m, n) + part(n, s) + part(m, s);
+    if (precision == QT_SPLIT_FP16)    // scales (2h floats) and max-abs partials
+        total += align_up(sizeof(float) * (size_t)h *
+                          (2 + qt::fp16_partial_blocks(m, n) + qt::fp16_partial_blocks(n, s)));
+    return total;
 }
 
 // Forward transforms of A and B (two planes, or one real plane to a half
 // spectrum), the uncoupled per-frequency complex products, and the inverse.
 int run_cx(int m, int n, int s, int p, const void* A, const void* B, void* C, qt_precision precision, void* ws,
            size_t ws_bytes, bool real, hipStream_t stream) {
-    if (precision != QT_FP32 && precision != QT_SPLIT_BF16) {
+    if (precision != QT_FP32 && precision != QT_SPLIT_BF16 && precision != QT_SPLIT_FP16) {
         return valid_precision(precision) ? QT_ERR_UNSUPPORTED : QT_ERR_INVALID_ARG;
     }
     if (!dims_ok(m, n, p) || !dims_ok(n, s, p) || !dims_ok(m, s, p)) return QT_ERR_INVALID_ARG;
@@ -532,7 +536,20 @@ int run_cx(int m, int n, int s, int p, const void* A, const void* B, void* C, qt
                             {(const float*)B, Bh, n, s, s, ldb, pack, 1, hf}};
     if (qt::launch_tube_fft<float>(p, false, fwd, 2, tw, stream) != hipSuccess) return QT_ERR_HIP;
     FacewiseArgs<float> fa{Ah, Bh, Ch, m, n, s, h, lda, ldb, ldc};
-    st = hip_status(qt::launch_facewise_cx(fa, precision == QT_SPLIT_BF16 ? 1 : 0, stream));
+    const float* scales = nullptr;
+    if (precision == QT_SPLIT_FP16) {
+        // per-frequency scales of A^ and B^ (no -f coupling), then the scaled
+        // fp16 words written over both operands
+        const size_t c_bytes = align_up(2 * (size_t)h * m * ldc * sizeof(float));
+        float* sc = reinterpret_cast<float*>(w + a_bytes + b_bytes + c_bytes);
+        st = hip_status(qt::launch_fp16_scales(fa, sc + 2 * (size_t)h, sc, stream, 2));
+        if (st == QT_OK) st = hip_status(qt::launch_fp16_words(Ah, h, m, n, lda, sc, stream, 2));
+        if (st == QT_OK) st = hip_status(qt::launch_fp16_words(Bh, h, n, s, ldb, sc + h, stream, 2));
+        if (st != QT_OK) return qt::to_status(st);
+        scales = sc;
+    }
+    const int mode = precision == QT_SPLIT_BF16 ? 1 : precision == QT_SPLIT_FP16 ? 2 : 0;
+    st = hip_status(qt::launch_facewise_cx(fa, mode, stream, scales));
     if (st != QT_OK) return qt::to_status(st);
     FftJob<float> inv[1] = {{Ch, (float*)C, m, s, ldc, s, 0, 1, hf}};
     return hip_status(qt::launch_tube_fft<float>(p, true, inv, 1, tw, stream));

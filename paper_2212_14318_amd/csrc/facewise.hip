@@ -209,11 +209,17 @@ constexpr int kCxWaves = 3;
 // so two workgroups share a CU and cover each other's barrier waits; a few
 // values spill to scratch): 5% faster on the 17-frequency real product.
 template <int MODE, int MT, int NT>
-__global__ void __launch_bounds__(512, (MODE == 1 && MT == 128 ? 4 : 2)) facewise_cx_kernel(FacewiseArgs<float> a, TileGrid tg) {
+__global__ void __launch_bounds__(512, (MODE != 0 && MT == 128 ? 4 : 2))
+facewise_cx_kernel(FacewiseArgs<float> a, TileGrid tg, const float* __restrict__ scales) {
     __shared__ __attribute__((aligned(16))) V2Smem<MT, NT, true> sm;
     int f, tm, tn;
     if (!tile_of_block(tg, f, tm, tn)) return;
-    tile_v2<MODE, MT, NT, 8, false, true>(a, f, tm * MT, tn * NT, 1.f, 1.f, sm);
+    float sa = 1.f, sb = 1.f;
+    if (MODE == 2) {     // fp16: scales[f] for A^, scales[p + f] for B^ at f
+        sa = scales[f];
+        sb = scales[a.p + f];
+    }
+    tile_v2<MODE, MT, NT, 8, false, true>(a, f, tm * MT, tn * NT, sa, sb, sm);
 }
 
 // ---------------------------------------------------- narrow products (s <= 4)
@@ -327,7 +333,7 @@ __global__ void __launch_bounds__(256) facewise_narrow_kernel(FacewiseArgs<float
 // reduction (per-block partials, then one thread per frequency).
 __global__ void __launch_bounds__(256)
 absmax_partial_kernel(const float* __restrict__ X, int rows, int cols, int ld, int p, int nblk,
-                      float* __restrict__ partial) {
+                      float* __restrict__ partial, int planes) {
     __shared__ float red[256];
     const int f = blockIdx.y;
     const size_t face = (size_t)rows * ld, plane = (size_t)p * face;
@@ -337,8 +343,7 @@ absmax_partial_kernel(const float* __restrict__ X, int rows, int cols, int ld, i
     for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < count; e += (long)nblk * 256) {
         const int i = (int)(e / cols), j = (int)(e - (long)i * cols);
         const size_t off = (size_t)i * ld + j;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) mx = fmaxf(mx, fabsf(Xf[c * plane + off]));
+        for (int c = 0; c < planes; ++c) mx = fmaxf(mx, fabsf(Xf[c * plane + off]));
     }
     red[threadIdx.x] = mx;
     __syncthreads();
@@ -349,11 +354,13 @@ absmax_partial_kernel(const float* __restrict__ X, int rows, int cols, int ld, i
     if (threadIdx.x == 0) partial[(size_t)f * nblk + blockIdx.x] = red[0];
 }
 
+// paired: the B^ scale covers the pair {f, -f} that the coupled product
+// stages together; complex products take B^[f] alone.
 __global__ void fp16_scales_kernel(const float* __restrict__ pa, int nba, const float* __restrict__ pb,
-                                   int nbb, int p, float* __restrict__ scales) {
+                                   int nbb, int p, float* __restrict__ scales, int paired) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= p) return;
-    const int g = (p - f) % p;
+    const int g = paired ? (p - f) % p : f;
     float ma = 0.f, mb = 0.f;
     for (int b = 0; b < nba; ++b) ma = fmaxf(ma, pa[(size_t)f * nba + b]);
     for (int b = 0; b < nbb; ++b) mb = fmaxf(mb, fmaxf(pb[(size_t)f * nbb + b], pb[(size_t)g * nbb + b]));
@@ -369,16 +376,16 @@ int fp16_partial_blocks(long rows, long cols) {
 }
 
 hipError_t launch_fp16_scales(const FacewiseArgs<float>& a, float* partials, float* scales,
-                              hipStream_t stream) {
+                              hipStream_t stream, int planes) {
     const int nba = fp16_partial_blocks(a.m, a.n), nbb = fp16_partial_blocks(a.n, a.s);
     float* pa = partials;
     float* pb = partials + (size_t)a.p * nba;
     hipLaunchKernelGGL(absmax_partial_kernel, dim3(nba, a.p), dim3(256), 0, stream, a.Ah, a.m, a.n, a.lda,
-                       a.p, nba, pa);
+                       a.p, nba, pa, planes);
     hipLaunchKernelGGL(absmax_partial_kernel, dim3(nbb, a.p), dim3(256), 0, stream, a.Bh, a.n, a.s, a.ldb,
-                       a.p, nbb, pb);
+                       a.p, nbb, pb, planes);
     hipLaunchKernelGGL(fp16_scales_kernel, dim3((a.p + 255) / 256), dim3(256), 0, stream, pa, nba, pb, nbb,
-                       a.p, scales);
+                       a.p, scales, planes == 4 ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -436,12 +443,13 @@ hipError_t launch_facewise_f32(const FacewiseArgs<float>& a, int precision, hipS
 }
 
 template <int MT, int NT>
-hipError_t launch_cx(const FacewiseArgs<float>& a, int precision, hipStream_t stream) {
+hipError_t launch_cx(const FacewiseArgs<float>& a, int precision, hipStream_t stream, const float* scales) {
     const int tiles_m = (a.m + MT - 1) / MT, tiles_n = (a.s + NT - 1) / NT;
     const TileGrid tg{tiles_m, tiles_n, a.p};
     const dim3 grid((unsigned)(tiles_m * tiles_n * a.p)), block(512);
-    if (precision == 0) hipLaunchKernelGGL((facewise_cx_kernel<0, MT, NT>), grid, block, 0, stream, a, tg);
-    else hipLaunchKernelGGL((facewise_cx_kernel<1, MT, NT>), grid, block, 0, stream, a, tg);
+    if (precision == 0) hipLaunchKernelGGL((facewise_cx_kernel<0, MT, NT>), grid, block, 0, stream, a, tg, scales);
+    else if (precision == 1) hipLaunchKernelGGL((facewise_cx_kernel<1, MT, NT>), grid, block, 0, stream, a, tg, scales);
+    else hipLaunchKernelGGL((facewise_cx_kernel<2, MT, NT>), grid, block, 0, stream, a, tg, scales);
     return hipGetLastError();
 }
 
@@ -450,14 +458,16 @@ static int cx_big_tile(int m, int s, int p, int cus) {
     return big >= (long)kCxWaves * cus ? 1 : 0;
 }
 
-hipError_t launch_facewise_cx(const FacewiseArgs<float>& a, int precision, hipStream_t stream) {
-    if (precision != 0 && precision != 1) return hipErrorNotSupported;
+hipError_t launch_facewise_cx(const FacewiseArgs<float>& a, int precision, hipStream_t stream,
+                              const float* scales) {
+    if (precision < 0 || precision > 2) return hipErrorNotSupported;
+    if (precision == 2 && !scales) return hipErrorInvalidValue;
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    return cx_big_tile(a.m, a.s, a.p, cus) ? launch_cx<256, 128>(a, precision, stream)
-                                           : launch_cx<128, 128>(a, precision, stream);
+    return cx_big_tile(a.m, a.s, a.p, cus) ? launch_cx<256, 128>(a, precision, stream, scales)
+                                           : launch_cx<128, 128>(a, precision, stream, scales);
 }
 
 hipError_t launch_facewise_f64(const FacewiseArgs<double>& a, hipStream_t stream) {

@@ -112,15 +112,19 @@ hipError_t launch_facewise_f32(const FacewiseArgs<float>& a, int precision, hipS
                                int tile_cfg = 0, const float* scales = nullptr);
 hipError_t launch_facewise_f64(const FacewiseArgs<double>& a, hipStream_t stream);
 // Complex products C^[f] = A^[f] B^[f] (planes 0, 1 of each tensor; no -f
-// coupling).  precision: 0 = FP32 MFMA, 1 = split bf16 (operand words).
-hipError_t launch_facewise_cx(const FacewiseArgs<float>& a, int precision, hipStream_t stream);
+// coupling).  precision: 0 = FP32 MFMA, 1 = split bf16 (operand words),
+// 2 = split fp16 (operand words scaled by scales[f] for A^, scales[p + f]
+// for B^).
+hipError_t launch_facewise_cx(const FacewiseArgs<float>& a, int precision, hipStream_t stream,
+                              const float* scales = nullptr);
 
 // fp16 split: per-frequency power-of-two scales of A^ and of the B^ pairs
 // {f, -f} into scales[0 .. 2p); partials needs p * (fp16_partial_blocks(m, n) +
-// fp16_partial_blocks(n, s)) floats.
+// fp16_partial_blocks(n, s)) floats.  Complex operands (planes = 2, no -f
+// coupling): the scale of B^ is per frequency, not per pair.
 int fp16_partial_blocks(long rows, long cols);
 hipError_t launch_fp16_scales(const FacewiseArgs<float>& a, float* partials, float* scales,
-                              hipStream_t stream);
+                              hipStream_t stream, int planes = 4);
 
 // Tensor conjugate transpose job: src is rows x cols x p ([4][p][rows][cols]),
 // dst is cols x rows x p.  planes_faces is filled in by the launcher.
@@ -153,10 +157,11 @@ int dispatch_tprod(int m, int n, int s, int p, const void* A, const void* B, voi
 // In-place FP32 -> split-bf16 words of `faces` faces of rows x cols (row
 // stride ld, a multiple of 4).
 hipError_t launch_split_words(float* X, long faces, long rows, long cols, long ld, hipStream_t stream);
-// In place: the Fourier-domain tensor [4][p][rows][ld] (cols valid columns)
-// becomes fp16 words hi | lo << 16 of x * scale[f] (the split-fp16 operands).
+// In place: the Fourier-domain tensor [planes][p][rows][ld] (cols valid
+// columns; 4 planes, or 2 for complex tensors) becomes fp16 words
+// hi | lo << 16 of x * scale[f] (the split-fp16 operands).
 hipError_t launch_fp16_words(float* X, long p, long rows, long cols, long ld, const float* scale,
-                             hipStream_t stream);
+                             hipStream_t stream, int planes = 4);
 
 // Tile shape (detail::TileCfg) for one facewise product: from the autotuner's
 // cost model when it has run on this device for this precision, else the

@@ -36,13 +36,14 @@ split_words_kernel(float* __restrict__ X, long faces, long rows, long cols, long
     }
 }
 
-// fp16 words of a Fourier-domain tensor [4][p][rows][ld] scaled per
+// fp16 words of a Fourier-domain tensor [planes][p][rows][ld] scaled per
 // frequency: x -> hi | lo << 16 with hi = rn_fp16(x s_f), lo = rn_fp16(x s_f
 // - hi); s_f = scale[f] is a power of two, so the scaling is exact.
 __global__ void __launch_bounds__(256)
-fp16_words_kernel(float* __restrict__ X, long p, long rows, long cols, long ld, const float* __restrict__ scale) {
+fp16_words_kernel(float* __restrict__ X, long p, long rows, long cols, long ld, const float* __restrict__ scale,
+                  int planes) {
     const long groups = (cols + 3) / 4;
-    const long total = 4 * p * rows * groups;
+    const long total = planes * p * rows * groups;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
         const long g = e % groups;
         const long fr = e / groups;                      // (plane * p + face) * rows + row
@@ -62,13 +63,13 @@ fp16_words_kernel(float* __restrict__ X, long p, long rows, long cols, long ld, 
 }  // namespace
 
 hipError_t launch_fp16_words(float* X, long p, long rows, long cols, long ld, const float* scale,
-                             hipStream_t stream) {
-    const long total = 4 * p * rows * ((cols + 3) / 4);
+                             hipStream_t stream, int planes) {
+    const long total = planes * p * rows * ((cols + 3) / 4);
     if (total <= 0) return hipSuccess;
     long blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(fp16_words_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, X, p, rows, cols, ld,
-                       scale);
+                       scale, planes);
     return hipGetLastError();
 }
 

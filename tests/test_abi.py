@@ -152,7 +152,11 @@ def test_real_workspace_formula(m, n, s, p):
     want = part(m, n) + part(n, s) + part(m, s)
     for prec in (nat.QT_FP32, nat.QT_SPLIT_BF16):
         assert nat.qt_real_workspace_size(m, n, s, p, prec) == want
-    assert nat.qt_real_workspace_size(m, n, s, p, nat.QT_SPLIT_FP16) == 0
+    # split fp16 adds the per-frequency scales and max-abs partials
+    nb = lambda r, c: min(64, (r * c + 255) // 256)
+    extra = (4 * h * (2 + nb(m, n) + nb(n, s)) + 255) // 256 * 256
+    assert nat.qt_real_workspace_size(m, n, s, p, nat.QT_SPLIT_FP16) == want + extra
+    assert nat.qt_real_workspace_size(m, n, s, p, nat.QT_FP64) == 0
 
 
 def test_real_rejects_bad_args():
@@ -161,7 +165,7 @@ def test_real_rejects_bad_args():
     ws_n = nat.qt_real_workspace_size(4, 4, 4, 4, nat.QT_FP32)
     assert nat.qt_tprod_real(4, 0, 4, 4, a, b, c, nat.QT_FP32, w, ws_n, None) == nat.QT_ERR_INVALID_ARG
     assert nat.qt_tprod_real(4, 4, 4, 4, a, None, c, nat.QT_FP32, w, ws_n, None) == nat.QT_ERR_INVALID_ARG
-    assert nat.qt_tprod_real(4, 4, 4, 4, a, b, c, nat.QT_SPLIT_FP16, w, ws_n, None) == nat.QT_ERR_UNSUPPORTED
+    assert nat.qt_tprod_real(4, 4, 4, 4, a, b, c, nat.QT_FP64, w, ws_n, None) == nat.QT_ERR_UNSUPPORTED
     assert nat.qt_tprod_real(4, 4, 4, 4, a, b, c, nat.QT_FP32, w, ws_n - 1, None) == nat.QT_ERR_INVALID_ARG
     assert nat.qt_tprod_real(4, 4, 4, 4, a, b, b, nat.QT_FP32, w, ws_n, None) == nat.QT_ERR_INVALID_ARG
     assert nat.qt_tprod_real(4, 4, 4, 4, a, b, c, nat.QT_FP32, ctypes.c_void_p((4 << 20) + 4), ws_n,
@@ -200,7 +204,7 @@ def test_null_workspace_needs_zero_bytes():
     # an unsupported precision keeps its own status when the library would allocate
     uns = nat.QT_ERR_UNSUPPORTED
     assert nat.qt_tprod_complex(4, 4, 4, 4, a, b, c, nat.QT_FP64, None, 0, None) == uns
-    assert nat.qt_tprod_real(4, 4, 4, 4, a, b, c, nat.QT_SPLIT_FP16, None, 0, None) == uns
+    assert nat.qt_tprod_real(4, 4, 4, 4, a, b, c, nat.QT_FP64, None, 0, None) == uns
 
 
 def test_split_words_rejects_bad_args():

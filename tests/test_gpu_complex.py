@@ -17,7 +17,7 @@ from gpu_util import device, rel_err, sample_indices, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
-TOLS = {"fp32": 1e-5, "split_bf16": 5e-5}
+TOLS = {"fp32": 1e-5, "split_bf16": 5e-5, "split_fp16": 5e-5}
 
 
 def _complex(rows, cols, p, seed):
@@ -41,7 +41,7 @@ def _bcirc_complex(A, B):
     return np.stack([c.real, c.imag])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
 @pytest.mark.parametrize("m,n,s,p", [(300, 70, 90, 8), (64, 64, 64, 12), (33, 129, 5, 11), (1, 1, 1, 1),
                                      (257, 31, 65, 2), (20, 40, 30, 97)])
 def test_complex_tprod(m, n, s, p, prec):
@@ -53,7 +53,7 @@ def test_complex_tprod(m, n, s, p, prec):
     assert rel_err(to_np(C), ref[:2]) < TOLS[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
 def test_complex_large_tile_sampled(prec):
     """2 x 3 x 128 = 768 tiles of 256 x 128: the large complex tile (ragged in
     m and s), checked on sampled entries computed one by one."""
@@ -67,6 +67,20 @@ def test_complex_large_tile_sampled(prec):
     got = C[:, k, i, j]
     err = float(np.sqrt(np.sum((got - ref[:2]) ** 2)) / np.sqrt(np.sum(ref[:2] ** 2)))
     assert err < TOLS[prec]
+
+
+def test_complex_fp16_face_scales():
+    """Split fp16 on complex tensors whose faces span 1e-3 .. 1e3: each
+    frequency of A^ and of B^ gets its own power-of-two scale."""
+    m, n, s, p = 70, 45, 60, 9
+    rng = np.random.Generator(np.random.PCG64(1950))
+    A = _complex(m, n, p, seed=1951) * (10.0 ** rng.uniform(-3, 3, p))[None, :, None, None]
+    B = _complex(n, s, p, seed=1952) * (10.0 ** rng.uniform(-3, 3, p))[None, :, None, None]
+    C = tprod_complex(to_dev(A), to_dev(B), precision="split_fp16")
+    ref = oracle.tprod(_as_quat(A), _as_quat(B))[:2]
+    err = rel_err(to_np(C), ref)
+    print(f"complex split_fp16, face scales 1e-3..1e3: rel err {err:.3e}")
+    assert err < TOLS["split_fp16"]
 
 
 def test_complex_oracle_agrees_with_bcirc_definition():

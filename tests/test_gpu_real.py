@@ -16,7 +16,7 @@ from gpu_util import device, rel_err, sample_indices, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
-TOLS = {"fp32": 1e-5, "split_bf16": 5e-5}
+TOLS = {"fp32": 1e-5, "split_bf16": 5e-5, "split_fp16": 5e-5}
 
 
 def _real(rows, cols, p, seed):
@@ -38,7 +38,7 @@ def _bcirc_real(A, B):
     return C
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
 @pytest.mark.parametrize("m,n,s,p", [(300, 70, 90, 8), (64, 64, 64, 12), (33, 129, 5, 11), (1, 1, 1, 1),
                                      (257, 31, 65, 2), (20, 40, 30, 97), (50, 20, 70, 3), (40, 33, 20, 128),
                                      (24, 17, 9, 200)])
@@ -51,7 +51,7 @@ def test_real_tprod(m, n, s, p, prec):
     assert rel_err(to_np(C), ref[0]) < TOLS[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
 def test_real_large_tile_sampled(prec):
     """p = 256 keeps 129 frequencies: 2 x 3 x 129 tiles of 256 x 128 (ragged in
     m and s), checked on sampled entries computed one by one."""
