@@ -89,6 +89,15 @@ def test_tsvd_block_sweeps_against_oracle(prec, m, n, p):
     _check(A64, prec, *_run(A64, prec))
 
 
+@pytest.mark.parametrize("prec,m,n,p", [("fp32", 512, 512, 3), ("fp64", 256, 200, 3)])
+def test_tsvd_block_sweeps_small_blocks(prec, m, n, p):
+    """Block sizes at the low end: 4 units per block (FP32, 512 x 512: 256
+    blocks for the pair f = 1, -1) and 5 (FP64, 256 x 200: a block size that is
+    not a multiple of the eight waves)."""
+    A64 = synth.quat_tensor(m, n, p, seed=8070 + m + n)
+    _check(A64, prec, *_run(A64, prec))
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_tsvd_block_sweeps_rank_deficient(prec):
     X = synth.quat_tensor(96, 20, 3, seed=8110)
