@@ -15,7 +15,7 @@ namespace detail {
 template <int P, int POL, bool INV>
 __global__ void __launch_bounds__(256)
 batched_fft_kernel(const BatchFftJob* __restrict__ jobs, const BatchFftItem* __restrict__ items) {
-    const BatchFftItem item = items[blockIdx.x];
+    const BatchFftItem item = items[xcd_contiguous(blockIdx.x, gridDim.x)];
     const BatchFftJob bj = jobs[item.job];
     const long e = (long)item.e0 + threadIdx.x;
     if (e >= (long)bj.rows * bj.cols) return;

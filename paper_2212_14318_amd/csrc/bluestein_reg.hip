@@ -24,9 +24,11 @@ bluestein_reg_kernel(detail::FftJobs2<T> jobs, int p, const typename detail::Vec
                      const typename detail::Vec2<T>::type* __restrict__ hat,
                      const typename detail::Vec2<T>::type* __restrict__ twf) {
     using V = typename detail::Vec2<T>::type;
-    const int part = blockIdx.y & 1;
-    const FftJob<T> jb = jobs.j[blockIdx.y >> 1];
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned b = detail::xcd_contiguous(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const unsigned bx = b % gridDim.x, by = b / gridDim.x;
+    const int part = by & 1;
+    const FftJob<T> jb = jobs.j[by >> 1];
+    const long e = (long)bx * blockDim.x + threadIdx.x;
     if (e >= (long)jb.rows * jb.cols || part >= jb.parts) return;
     const long i = e / jb.cols, c = e - i * jb.cols;
     const size_t sface = (size_t)jb.rows * jb.src_ld;

@@ -253,14 +253,27 @@ __device__ __forceinline__ void tube_fft_one(const FftJob<T>& jb, int part, long
     }
 }
 
+// Workgroups go to the eight XCDs in turn (workgroup w to XCD w mod 8).  This
+// maps w to a block index such that every XCD takes one contiguous run of
+// blocks: a face is in general not aligned to 128-byte lines, so two
+// neighbouring blocks share a line in every face they read or write, and that
+// line then meets in one L2 instead of being fetched (or partly written back)
+// by two.
+__device__ __forceinline__ unsigned xcd_contiguous(unsigned w, unsigned n) {
+    const unsigned q = n / 8, r = n % 8, x = w % 8;
+    return x * q + (x < r ? x : r) + w / 8;
+}
+
 // grid: x covers rows*cols of the largest job, y = 2 * njobs (job, CD part).
 template <int P, bool INV, typename T>
 __global__ void __launch_bounds__(256)
 tube_fft_kernel(FftJobs2<T> jobs, const typename Vec2<T>::type* __restrict__ tw) {
-    const int job = blockIdx.y >> 1;
-    const int part = blockIdx.y & 1;                 // 0: X1 (planes 0,1), 1: X2 (planes 2,3)
+    const unsigned b = xcd_contiguous(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const unsigned bx = b % gridDim.x, by = b / gridDim.x;
+    const int job = by >> 1;
+    const int part = by & 1;                         // 0: X1 (planes 0,1), 1: X2 (planes 2,3)
     const FftJob<T> jb = jobs.j[job];
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long e = (long)bx * blockDim.x + threadIdx.x;
     if (e >= (long)jb.rows * jb.cols || part >= jb.parts) return;
     tube_fft_one<P, INV, T>(jb, part, e, tw);
 }
