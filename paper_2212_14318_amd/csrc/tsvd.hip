@@ -219,20 +219,25 @@ __device__ __forceinline__ bool jacobi_pair(V* xi, V* xj, V* qi, V* qj, int h, i
 
 // The same step with both columns held in registers between the inner
 // products and the update (K loads per lane and column half issued together):
-// for h, hq <= 64 K.
-template <typename T, typename V, int K>
+// for h <= 64 K and hq <= 64 KQ.
+template <typename T, typename V, int K, int KQ = K>
 __device__ __forceinline__ bool jacobi_pair_reg(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool quat, T tol, Acc negl2, int lane) {
     // the rotation columns are loaded with the data columns (one memory
     // round trip per pair); they are only written back if a rotation happens
-    V a0[K], a1[K], b0[K], b1[K], c0[K], c1[K], d0[K], d1[K];
+    V a0[K], a1[K], b0[K], b1[K], c0[KQ], c1[KQ], d0[KQ], d1[KQ];
 #pragma unroll
     for (int t = 0; t < K; ++t) {
         const int k = lane + 64 * t;
-        const bool in = k < h, inq = k < hq;
+        const bool in = k < h;
         a0[t] = in ? xi[k] : V{0, 0};
         a1[t] = in ? xi[k + h] : V{0, 0};
         b0[t] = in ? xj[k] : V{0, 0};
         b1[t] = in ? xj[k + h] : V{0, 0};
+    }
+#pragma unroll
+    for (int t = 0; t < KQ; ++t) {
+        const int k = lane + 64 * t;
+        const bool inq = k < hq;
         c0[t] = inq ? qi[k] : V{0, 0};
         c1[t] = inq ? qi[k + hq] : V{0, 0};
         d0[t] = inq ? qj[k] : V{0, 0};
@@ -288,6 +293,10 @@ __device__ __forceinline__ bool jacobi_pair_reg(V* xi, V* xj, V* qi, V* qj, int 
             xj[k] = b0[t];
             xj[k + h] = b1[t];
         }
+    }
+#pragma unroll
+    for (int t = 0; t < KQ; ++t) {
+        const int k = lane + 64 * t;
         if (k < hq) {
             rot(c0[t], c1[t], d0[t], d1[t]);
             qi[k] = c0[t];
@@ -622,16 +631,34 @@ __global__ void __launch_bounds__(kThreads) tsvd_pair_kernel(TsvdArgs<T> a) {
 // For larger matrices the sweeps are spread over many workgroups per pair.
 // The units are cut into blocks of bs; in round t of a sweep, block pair q
 // of the circle schedule over the blocks goes to one workgroup, which stages
-// the data and rotation columns of its two blocks in LDS, applies the
-// rotations of every unit pair across the two blocks (and, in round 0, the
-// pairs within each block), and writes the columns back.  Every unit pair is
-// visited once per sweep, as in the single-workgroup order, with one global
-// read and write of a column per block pair instead of one per unit pair.
+// the data columns of its two blocks in LDS, applies the rotations of every
+// unit pair across the two blocks (and, in round 0, the pairs within each
+// block), and writes the columns back.  Every unit pair is visited once per
+// sweep, as in the single-workgroup order, with one global read and write of
+// a column per block pair instead of one per unit pair.
+// The rotations are not applied to the staged rotation columns one by one:
+// the workgroup accumulates their product W over its nk units in LDS and
+// applies it once at the end, Q_j <- sum_i Q_i A_ij + partner(Q_i) B_ij.
+// A Jacobi step maps unit columns to combinations of this form, and since
+// partner is conjugate-linear with partner(partner(x)) = -x, the coefficient
+// column (A_j; B_j) of unit j transforms under a step exactly as a
+// quaternion column (top; bottom) does, so the same step code updates it
+// (B stays zero for complex pairs).  Only the data columns take LDS, which
+// lets two workgroups share a CU when they fit in half of it.
 // A sweep is one launch per round plus a check: a pair whose sweep applied no
 // rotation is done, and its workgroups return at once in later launches.
-constexpr size_t kBlockLds = 144 << 10;   // staged columns per workgroup
+constexpr size_t kBlockLds = 144 << 10;   // LDS of one workgroup per CU
+constexpr size_t kBlockLdsHalf = 72 << 10; // two workgroups per CU
+constexpr int kBlockMaxBs = 8;            // units per block (one cross pair per wave and round)
 constexpr int kBlockMinUnits = 128;       // smaller matrices stay in one workgroup
 constexpr int kBlockMaxSweeps = 32;
+
+// LDS of a block pair: 2 bs data columns of R entries and 2 bs coefficient
+// columns of 4 bs entries.
+template <typename T>
+size_t block_lds_bytes(int bs, int R) {
+    return ((size_t)2 * bs * R + (size_t)2 * bs * 4 * bs) * sizeof(typename Cx<T>::type);
+}
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) tsvd_prep_kernel(TsvdArgs<T> a) {
@@ -658,11 +685,70 @@ __device__ __forceinline__ void dma_copy(const V* src, V* dst, size_t bytes, int
     }
 }
 
-// grid: (block pairs of the longest schedule, frequency pairs)
-template <typename T>
-__global__ void __launch_bounds__(kThreads) tsvd_round_kernel(TsvdArgs<T> a, int bs, int t, int sweep) {
+// Q <- Q W for the nk staged units of a block pair (units u < nI at QI + u Rq,
+// the others at QJ + u Rq), W in LDS as coefficient columns wc + j 2nk (A
+// part, then B part): Q_j = sum_u Q_u A_uj + partner(Q_u) B_uj, where
+// partner(q) = (-conj(bottom half); conj(top half)) and B = 0 for a complex
+// pair (QUAT false).  A thread holds row k of every unit (rows k and k + hq of
+// a quaternion column) in registers and overwrites them column by column.
+// With two threads per row (quaternion pairs of up to kThreads / 2 rows) the
+// threads of a row split the output columns and read the row before either
+// writes.  FULL: nk is the largest block pair, known at compile time, so the
+// coefficient reads of one output column issue together.
+template <bool FULL, bool QUAT, typename V>
+__device__ __forceinline__ void apply_coefficients(V* QI, V* QJ, int nI, int nk, int Rq, const V* wc, int tid) {
+    constexpr int MU = 2 * kBlockMaxBs;
+    const int hq = Rq / 2, rows = QUAT ? hq : Rq, w2 = 2 * nk;
+    const int per_row = QUAT && 2 * rows <= kThreads ? 2 : 1;
+    const int kend = per_row * rows;
+    for (int base = 0; base < kend; base += kThreads) {
+        const int id = base + tid, k = id % rows, j0 = id / rows;
+        const bool act = id < kend;
+        V top[MU], bot[MU];
+#pragma unroll
+        for (int u = 0; u < MU; ++u) {
+            top[u] = bot[u] = V{0, 0};
+            if (act && (FULL || u < nk)) {
+                const V* qu = (u < nI ? QI : QJ) + (size_t)u * Rq;
+                top[u] = qu[k];
+                if (QUAT) bot[u] = qu[k + hq];
+            }
+        }
+        if (per_row == 2) __syncthreads();
+        if (!act) continue;
+#pragma unroll 1
+        for (int j = j0; j < nk; j += per_row) {
+            const V* cj = wc + (size_t)j * w2;
+            V o0{0, 0}, o1{0, 0};
+#pragma unroll
+            for (int u = 0; u < MU; ++u) {
+                if (FULL || u < nk) {
+                    const V aa = cj[u];
+                    o0 = cadd(o0, cmul(top[u], aa));
+                    if (QUAT) {
+                        const V bb = cj[nk + u];
+                        o0 = csub(o0, cmul(cconj(bot[u]), bb));
+                        o1 = cadd(o1, cadd(cmul(bot[u], aa), cmul(cconj(top[u]), bb)));
+                    }
+                }
+            }
+            V* qj = (j < nI ? QI : QJ) + (size_t)j * Rq;
+            qj[k] = o0;
+            if (QUAT) qj[k + hq] = o1;
+        }
+    }
+}
+
+// grid: (block pairs of the longest schedule, frequency pairs).  LDS bytes
+// of staging (kBlockLds or kBlockLdsHalf); with the half, the register
+// budget allows two workgroups of 8 waves per CU.  KR: data-column entries
+// per lane and column half held in registers by a Jacobi step (1 for
+// max(m, n) <= 64, 4 for <= 256), 0 for the looping step of longer columns.
+template <typename T, size_t LDS, int KR>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LDS == kBlockLdsHalf ? 4 : 2)))
+tsvd_round_kernel(TsvdArgs<T> a, int bs, int t, int sweep) {
     using V = typename Cx<T>::type;
-    __shared__ __attribute__((aligned(16))) char s_cols[kBlockLds];
+    __shared__ __attribute__((aligned(16))) char s_cols[LDS];
     __shared__ int s_rot;
     const PairView<T> pv = pair_view(a, blockIdx.y);
     if (pv.hdr->done) return;
@@ -674,26 +760,26 @@ __global__ void __launch_bounds__(kThreads) tsvd_round_kernel(TsvdArgs<T> a, int
     const int nJ = J < nb ? min(bs, nu - J * bs) : 0;
     if (t > 0 && (nI == 0 || nJ == 0)) return;      // within-block pairs go in round 0 only
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int R = pv.R, Rq = pv.Rq, nk = nI + nJ;
-    V* xs = reinterpret_cast<V*>(s_cols);            // staged unit k: xs + k R, qs + k Rq
-    V* qs = xs + (size_t)nk * R;
-    // each block's columns are contiguous in X and in Q: four DMA copies
+    const int R = pv.R, Rq = pv.Rq, nk = nI + nJ, w2 = 2 * nk;
+    V* xs = reinterpret_cast<V*>(s_cols);            // staged unit k: xs + k R
+    V* wc = xs + (size_t)nk * R;                     // its coefficient column: wc + k 2nk (A, then B)
+    // each block's columns are contiguous in X: two DMA copies
     dma_copy(pv.X + (size_t)I * bs * R, xs, (size_t)nI * R * sizeof(V), wave, lane);
     dma_copy(pv.X + (size_t)J * bs * R, xs + (size_t)nI * R, (size_t)nJ * R * sizeof(V), wave, lane);
-    dma_copy(pv.Q + (size_t)I * bs * Rq, qs, (size_t)nI * Rq * sizeof(V), wave, lane);
-    dma_copy(pv.Q + (size_t)J * bs * Rq, qs + (size_t)nI * Rq, (size_t)nJ * Rq * sizeof(V), wave, lane);
+    for (int e = tid; e < nk * w2; e += kThreads) wc[e] = V{e % w2 == e / w2 ? T(1) : T(0), T(0)};
     __builtin_amdgcn_s_waitcnt(0);                   // this wave's copies have landed
     if (tid == 0) s_rot = 0;
     __syncthreads();
     const T tol = jacobi_tol<T>(R);
     const Acc negl2 = pv.hdr->negl2;
     bool rot = false;
-    const int r = pv.r, c = pv.c;
+    const int r = pv.r;
     auto step = [&](int i, int j) {
-        V *xi = xs + (size_t)i * R, *xj = xs + (size_t)j * R, *qi = qs + (size_t)i * Rq, *qj = qs + (size_t)j * Rq;
-        rot |= (r <= 64 && c <= 64)     ? jacobi_pair_reg<T, V, 1>(xi, xj, qi, qj, r, c, pv.quat, tol, negl2, lane)
-               : (r <= 256 && c <= 256) ? jacobi_pair_reg<T, V, 4>(xi, xj, qi, qj, r, c, pv.quat, tol, negl2, lane)
-                                        : jacobi_pair<T, V>(xi, xj, qi, qj, r, c, pv.quat, tol, negl2, lane);
+        V *xi = xs + (size_t)i * R, *xj = xs + (size_t)j * R, *wi = wc + (size_t)i * w2, *wj = wc + (size_t)j * w2;
+        if constexpr (KR > 0)
+            rot |= jacobi_pair_reg<T, V, KR, 1>(xi, xj, wi, wj, r, nk, pv.quat, tol, negl2, lane);
+        else
+            rot |= jacobi_pair<T, V>(xi, xj, wi, wj, r, nk, pv.quat, tol, negl2, lane);
     };
     if (t == 0) {
         // pairs within block I (staged 0 .. nI - 1) and within block J
@@ -736,8 +822,8 @@ __global__ void __launch_bounds__(kThreads) tsvd_round_kernel(TsvdArgs<T> a, int
     if (rot && lane == 0) s_rot = 1;
     __syncthreads();
     if (!s_rot) return;
-    // write back the four contiguous ranges in 16-byte words, four LDS reads
-    // in flight per thread before the stores
+    // write the data columns back in 16-byte words, four LDS reads in flight
+    // per thread before the stores
     auto copy_out = [&](V* g, const V* sh, size_t bytes) {
         typedef unsigned u4 __attribute__((ext_vector_type(4)));
         u4* gd = reinterpret_cast<u4*>(g);
@@ -759,8 +845,16 @@ __global__ void __launch_bounds__(kThreads) tsvd_round_kernel(TsvdArgs<T> a, int
     };
     copy_out(pv.X + (size_t)I * bs * R, xs, (size_t)nI * R * sizeof(V));
     copy_out(pv.X + (size_t)J * bs * R, xs + (size_t)nI * R, (size_t)nJ * R * sizeof(V));
-    copy_out(pv.Q + (size_t)I * bs * Rq, qs, (size_t)nI * Rq * sizeof(V));
-    copy_out(pv.Q + (size_t)J * bs * Rq, qs + (size_t)nI * Rq, (size_t)nJ * Rq * sizeof(V));
+    V* QI = pv.Q + (size_t)I * bs * Rq;
+    V* QJ = pv.Q + (size_t)J * bs * Rq - (size_t)nI * Rq;   // staged unit u >= nI: QJ + u Rq
+    constexpr int MU = 2 * kBlockMaxBs;
+    if (nk == MU) {
+        if (pv.quat) apply_coefficients<true, true, V>(QI, QJ, nI, nk, Rq, wc, tid);
+        else apply_coefficients<true, false, V>(QI, QJ, nI, nk, Rq, wc, tid);
+    } else {
+        if (pv.quat) apply_coefficients<false, true, V>(QI, QJ, nI, nk, Rq, wc, tid);
+        else apply_coefficients<false, false, V>(QI, QJ, nI, nk, Rq, wc, tid);
+    }
     if (tid == 0) pv.hdr->rot[sweep & 1] = 1;
 }
 
@@ -834,14 +928,16 @@ bool tsvd_dims_ok(int m, int n, int p) {
 }
 
 // Staged units per block of the block sweeps for an m x n pair matrix (0:
-// the single-workgroup kernel serves this size).
+// the single-workgroup kernel serves this size), and whether a block pair
+// fits in half the LDS (two workgroups per CU).
 template <typename T>
-int tsvd_block_size(int m, int n) {
+int tsvd_block_size(int m, int n, bool* half_lds) {
     const int r = m > n ? m : n, c = m > n ? n : m;
-    const size_t unit = (size_t)(2 * r + 2 * c) * sizeof(typename Cx<T>::type);   // data + rotation column
-    int bs = (int)(kBlockLds / (2 * unit));
-    bs = bs < c ? bs : c;                 // at least two blocks
-    if (bs >= 8) bs &= ~7;                // one cross pair per wave and round
+    int bs = kBlockMaxBs < c ? kBlockMaxBs : c;   // at least two blocks
+    while (bs >= 4 && block_lds_bytes<T>(bs, 2 * r) > kBlockLds) --bs;
+    // (FP32 only: the FP64 round kernel does not fit the register budget of
+    // two workgroups per CU)
+    *half_lds = sizeof(T) == 4 && block_lds_bytes<T>(bs, 2 * r) <= kBlockLdsHalf;
     return (bs >= 4 && 2 * c >= kBlockMinUnits) ? bs : 0;
 }
 
@@ -852,7 +948,8 @@ hipError_t launch_tsvd_pairs(int m, int n, int p, const T* Ah, int lda, T* Uh, i
     const size_t pb = pair_scratch_bytes<T>(m, n);
     TsvdArgs<T> args{Ah, Uh, Vh, sigma, pairs, pb, m, n, p, lda, ldu, ldv};
     const int npairs = p / 2 + 1;
-    const int bs = tsvd_block_size<T>(m, n);
+    bool half = false;
+    const int bs = tsvd_block_size<T>(m, n, &half);
     if (!bs) {
         hipLaunchKernelGGL(tsvd_pair_kernel<T>, dim3(npairs), dim3(kThreads), 0, stream, args);
         return hipGetLastError();
@@ -860,10 +957,25 @@ hipError_t launch_tsvd_pairs(int m, int n, int p, const T* Ah, int lda, T* Uh, i
     const int c = m > n ? n : m;
     const int nb = (2 * c + bs - 1) / bs, nbp = nb + (nb & 1);
     hipLaunchKernelGGL(tsvd_prep_kernel<T>, dim3(npairs), dim3(kThreads), 0, stream, args);
+    const int r = m > n ? m : n;
+    auto round = [&](int t, int sweep) {
+        const dim3 grid(nbp / 2, npairs), block(kThreads);
+#define QT_ROUND(LDS, KR) hipLaunchKernelGGL((tsvd_round_kernel<T, LDS, KR>), grid, block, 0, stream, args, bs, t, sweep)
+        if constexpr (sizeof(T) == 4) {
+            // half: max(m, n) <= 272 (KR = 4 exceeds the register budget of
+            // two workgroups per CU); otherwise the columns are longer than 256
+            if (!half) QT_ROUND(kBlockLds, 0);
+            else if (r <= 64) QT_ROUND(kBlockLdsHalf, 1);
+            else QT_ROUND(kBlockLdsHalf, 0);
+        } else {
+            if (r <= 64) QT_ROUND(kBlockLds, 1);
+            else if (r <= 256) QT_ROUND(kBlockLds, 4);
+            else QT_ROUND(kBlockLds, 0);
+        }
+#undef QT_ROUND
+    };
     for (int sweep = 0; sweep < kBlockMaxSweeps; ++sweep) {
-        for (int t = 0; t < nbp - 1; ++t)
-            hipLaunchKernelGGL(tsvd_round_kernel<T>, dim3(nbp / 2, npairs), dim3(kThreads), 0, stream, args, bs, t,
-                               sweep);
+        for (int t = 0; t < nbp - 1; ++t) round(t, sweep);
         hipLaunchKernelGGL(tsvd_check_kernel<T>, dim3((npairs + 255) / 256), dim3(256), 0, stream, args, npairs,
                            sweep);
     }

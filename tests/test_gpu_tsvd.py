@@ -89,11 +89,13 @@ def test_tsvd_block_sweeps_against_oracle(prec, m, n, p):
     _check(A64, prec, *_run(A64, prec))
 
 
-@pytest.mark.parametrize("prec,m,n,p", [("fp32", 512, 512, 3), ("fp64", 256, 200, 3)])
+@pytest.mark.parametrize("prec,m,n,p", [("fp32", 1024, 64, 2), ("fp64", 400, 100, 3), ("fp32", 512, 512, 3)])
 def test_tsvd_block_sweeps_small_blocks(prec, m, n, p):
-    """Block sizes at the low end: 4 units per block (FP32, 512 x 512: 256
-    blocks for the pair f = 1, -1) and 5 (FP64, 256 x 200: a block size that is
-    not a multiple of the eight waves)."""
+    """Block sizes below eight units, where the staged columns are long: 4
+    units per block (FP32, 1024 x 64: columns of 2048 entries) and 5 (FP64,
+    400 x 100: a block size that is not a multiple of the eight waves); and
+    FP32 512 x 512, eight units per block in a workgroup that has the CU's
+    LDS to itself."""
     A64 = synth.quat_tensor(m, n, p, seed=8070 + m + n)
     _check(A64, prec, *_run(A64, prec))
 
