@@ -289,7 +289,8 @@ DescLayout desc_layout(int count, const qt_problem* probs) {
     for (int i = 0; i < count; ++i) {
         const qt_problem& q = probs[i];
         nfaces += 2L * q.p;                                     // split fp16: faces of A^ and B^
-        nfi += 2 * (((long)q.m * q.n + 255) / 256) + 2 * (((long)q.n * q.s + 255) / 256);
+        // forward positions run over the padded rows (BatchFftJob::fill)
+        nfi += 2 * (((long)q.m * fourier_ld(q.n) + 255) / 256) + 2 * (((long)q.n * fourier_ld(q.s) + 255) / 256);
         ngi += (long)q.p * ((q.m + 31) / 32) * ((q.s + 63) / 64);   // 32 x 64 is the smallest tile
         nii += 2 * (((long)q.m * q.s + 255) / 256);
         tens += fourier_bytes(q.m, q.n, q.p) + fourier_bytes(q.n, q.s, q.p) + fourier_bytes(q.m, q.s, q.p);
@@ -371,8 +372,8 @@ int build_lists(int count, const qt_problem* probs, int prec, char* ws, const De
             sf.inv = FftJob<float>{Ch, (float*)q.C, q.m, q.s, ldc, q.s};
             H->single.push_back(sf);
         }
-        H->fwd_jobs.push_back(BatchFftJob{(const float*)q.A, Ah, tw.f32, q.m, q.n, q.n, lda, q.p, pol, pack, 0});
-        H->fwd_jobs.push_back(BatchFftJob{(const float*)q.B, Bh, tw.f32, q.n, q.s, q.s, ldb, q.p, pol, pack, 0});
+        H->fwd_jobs.push_back(BatchFftJob{(const float*)q.A, Ah, tw.f32, q.m, q.n, q.n, lda, q.p, pol, pack, lda > q.n});
+        H->fwd_jobs.push_back(BatchFftJob{(const float*)q.B, Bh, tw.f32, q.n, q.s, q.s, ldb, q.p, pol, pack, ldb > q.s});
         H->inv_jobs.push_back(BatchFftJob{Ch, (float*)q.C, tw.f32, q.m, q.s, ldc, q.s, q.p, pol, 0, 0});
         const int cfg = pick_tile(&tune, q.m, q.n, q.s);
         const float* scales = nullptr;
@@ -394,7 +395,8 @@ int build_lists(int count, const qt_problem* probs, int prec, char* ws, const De
     // batched FFT items only for the lengths the batched kernel has
     for (int j = 0; j < (int)H->fwd_jobs.size(); ++j)
         if (batched_fft_supported(H->fwd_jobs[j].p))
-            add_fft_items(H->fwd_items, j, (long)H->fwd_jobs[j].rows * H->fwd_jobs[j].cols);
+            add_fft_items(H->fwd_items, j,
+                          (long)H->fwd_jobs[j].rows * (H->fwd_jobs[j].fill ? H->fwd_jobs[j].dst_ld : H->fwd_jobs[j].cols));
     for (int j = 0; j < (int)H->inv_jobs.size(); ++j)
         if (batched_fft_supported(H->inv_jobs[j].p))
             add_fft_items(H->inv_items, j, (long)H->inv_jobs[j].rows * H->inv_jobs[j].cols);

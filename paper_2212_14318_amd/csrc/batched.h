@@ -12,7 +12,12 @@ struct BatchFftJob {
     const float2* tw;          // twiddle table of p
     int rows, cols, src_ld, dst_ld;
     int p, pol;                // length and radix-order policy (0 or 1)
-    int pack, pad;             // 1: forward output as split-bf16 words (FftJob::pack)
+    int pack;                  // 1: forward output as split-bf16 words (FftJob::pack)
+    // 1 (forward, dst_ld > cols): the positions run over rows x dst_ld and
+    // the padding columns of the destination rows are written as zeros, so
+    // that every destination line is written whole (a partly written line
+    // costs a read-modify-write beyond L2)
+    int fill;
 };
 
 // 256 consecutive positions of one CD part of one job.

@@ -211,27 +211,39 @@ __device__ __forceinline__ void tube_fft_half(const FftJob<T>& jb, const T* __re
 }
 
 // Transform one complex tube: part 0 = X1 (planes 0, 1), part 1 = X2
-// (planes 2, 3) at flattened position e = i * cols + c of job jb.
-template <int P, bool INV, typename T, int POL = 0>
-__device__ __forceinline__ void tube_fft_one(const FftJob<T>& jb, int part, long e,
-                                             const typename Vec2<T>::type* __restrict__ tw) {
+// (planes 2, 3) at row i, column c of job jb.  FILL (forward): c runs over
+// the destination's padded rows, and a column c >= cols is transformed as a
+// zero tube (its loads read column cols - 1 and are discarded), so that the
+// padding columns are written in the same store instructions as the others.
+template <int P, bool INV, typename T, int POL = 0, bool FILL = false>
+__device__ __forceinline__ void tube_fft_rc(const FftJob<T>& jb, int part, int i, int c,
+                                            const typename Vec2<T>::type* __restrict__ tw) {
     using V = typename Vec2<T>::type;
-    const int i = (int)(e / jb.cols);
-    const int c = (int)(e - (long)i * jb.cols);
+    static_assert(!(FILL && INV), "padding columns are filled by the forward transform");
+    const bool zero = FILL && c >= jb.cols;
+    const int cs = zero ? jb.cols - 1 : c;
     const size_t sface = (size_t)jb.rows * jb.src_ld;
     const size_t dface = (size_t)jb.rows * jb.dst_ld;
-    const T* __restrict__ sre = jb.src + (size_t)(2 * part) * P * sface + (size_t)i * jb.src_ld + c;
+    const T* __restrict__ sre = jb.src + (size_t)(2 * part) * P * sface + (size_t)i * jb.src_ld + cs;
     const T* __restrict__ sim = sre + (size_t)P * sface;
     T* __restrict__ dre = jb.dst + (size_t)(2 * part) * P * dface + (size_t)i * jb.dst_ld + c;
     T* __restrict__ dim = dre + (size_t)P * dface;
 
-    if (jb.half) {
-        tube_fft_half<P, INV, T, POL>(jb, sre, dre, sface, dface, tw);
-        return;
+    if constexpr (!FILL) {
+        if (jb.half) {
+            tube_fft_half<P, INV, T, POL>(jb, sre, dre, sface, dface, tw);
+            return;
+        }
     }
     V x[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) x[k] = V{sre[k * sface], sim[k * sface]};
+    if constexpr (FILL) {
+        if (zero) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) x[k] = V{T(0), T(0)};
+        }
+    }
     Dft<P, P, INV, V, POL>::run(x, tw);
     if constexpr (!INV && sizeof(T) == 4) {
         if (jb.pack) {   // bf16 split of every real: hi | lo << 16
@@ -251,6 +263,14 @@ __device__ __forceinline__ void tube_fft_one(const FftJob<T>& jb, int part, long
         dre[k * dface] = x[k].x * scale;
         dim[k * dface] = x[k].y * scale;
     }
+}
+
+// The same at flattened position e = i * cols + c.
+template <int P, bool INV, typename T, int POL = 0>
+__device__ __forceinline__ void tube_fft_one(const FftJob<T>& jb, int part, long e,
+                                             const typename Vec2<T>::type* __restrict__ tw) {
+    const int i = (int)(e / jb.cols);
+    tube_fft_rc<P, INV, T, POL>(jb, part, i, (int)(e - (long)i * jb.cols), tw);
 }
 
 // Workgroups go to the eight XCDs in turn (workgroup w to XCD w mod 8).  This
