@@ -153,7 +153,7 @@ int run_tprod(int m, int n, int s, int p, const T* A, const T* B, T* C, int prec
     // step 1: tube FFT of A and B (one launch); split-bf16 operands leave the
     // FFT already split into hi/lo words
     const int pack = prec == QT_SPLIT_BF16 ? 1 : 0;
-    FftJob<T> fwd[2] = {{A, Ah, m, n, n, lda, pack}, {B, Bh, n, s, s, ldb, pack}};
+    FftJob<T> fwd[2] = {{A, Ah, m, n, n, lda, pack, 2, 0, 1}, {B, Bh, n, s, s, ldb, pack, 2, 0, 1}};
     if (qt::launch_tube_fft<T>(p, false, fwd, 2, tw, stream) != hipSuccess) return QT_ERR_HIP;
 
     // step 2: coupled facewise products
@@ -271,11 +271,11 @@ int run_backward(int m, int n, int s, int p, const T* A, const T* B, const T* G,
     if (st != QT_OK) return st;
 
     const int pack = prec == QT_SPLIT_BF16 ? 1 : 0;
-    FftJob<T> f1[2] = {{G, Gh, m, s, s, lds, pack}, {Y, Yh, s, n, n, ldn, pack}};
+    FftJob<T> f1[2] = {{G, Gh, m, s, s, lds, pack, 2, 0, 1}, {Y, Yh, s, n, n, ldn, pack, 2, 0, 1}};
     st = hip_status(qt::launch_tube_fft<T>(p, false, f1, dA ? 2 : 1, tw, stream));
     if (st != QT_OK) return st;
     if (dB) {
-        FftJob<T> f2[1] = {{Z, Zh, n, m, m, ldm, pack}};
+        FftJob<T> f2[1] = {{Z, Zh, n, m, m, ldm, pack, 2, 0, 1}};
         st = hip_status(qt::launch_tube_fft<T>(p, false, f2, 1, tw, stream));
         if (st != QT_OK) return st;
     }
@@ -286,7 +286,7 @@ int run_backward(int m, int n, int s, int p, const T* A, const T* B, const T* G,
             T* Gb = Gh;
             if (dA && dB) {
                 Gb = reinterpret_cast<T*>(ws + L.gh2);
-                FftJob<T> f3[1] = {{G, Gb, m, s, s, lds, 0}};
+                FftJob<T> f3[1] = {{G, Gb, m, s, s, lds, 0, 2, 0, 1}};
                 st = hip_status(qt::launch_tube_fft<T>(p, false, f3, 1, tw, stream));
                 if (st != QT_OK) return st;
             }
@@ -532,8 +532,8 @@ int run_cx(int m, int n, int s, int p, const void* A, const void* B, void* C, qt
     const int pack = precision == QT_SPLIT_BF16 ? 1 : 0;
     const int hf = real ? 1 : 0;
     // one CD part (planes 0, 1) per tensor
-    FftJob<float> fwd[2] = {{(const float*)A, Ah, m, n, n, lda, pack, 1, hf},
-                            {(const float*)B, Bh, n, s, s, ldb, pack, 1, hf}};
+    FftJob<float> fwd[2] = {{(const float*)A, Ah, m, n, n, lda, pack, 1, hf, 1},
+                            {(const float*)B, Bh, n, s, s, ldb, pack, 1, hf, 1}};
     if (qt::launch_tube_fft<float>(p, false, fwd, 2, tw, stream) != hipSuccess) return QT_ERR_HIP;
     FacewiseArgs<float> fa{Ah, Bh, Ch, m, n, s, h, lda, ldb, ldc};
     const float* scales = nullptr;

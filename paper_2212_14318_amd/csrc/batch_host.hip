@@ -367,8 +367,8 @@ int build_lists(int count, const qt_problem* probs, int prec, char* ws, const De
         const int pack = prec == QT_SPLIT_BF16 ? 1 : 0;
         if (!batched_fft_supported(q.p)) {
             SingleFft sf{q.p, tw, {}, {}};
-            sf.fwd[0] = FftJob<float>{(const float*)q.A, Ah, q.m, q.n, q.n, lda, pack};
-            sf.fwd[1] = FftJob<float>{(const float*)q.B, Bh, q.n, q.s, q.s, ldb, pack};
+            sf.fwd[0] = FftJob<float>{(const float*)q.A, Ah, q.m, q.n, q.n, lda, pack, 2, 0, 1};
+            sf.fwd[1] = FftJob<float>{(const float*)q.B, Bh, q.n, q.s, q.s, ldb, pack, 2, 0, 1};
             sf.inv = FftJob<float>{Ch, (float*)q.C, q.m, q.s, ldc, q.s};
             H->single.push_back(sf);
         }

@@ -284,7 +284,14 @@ __device__ __forceinline__ unsigned xcd_contiguous(unsigned w, unsigned n) {
     return x * q + (x < r ? x : r) + w / 8;
 }
 
-// grid: x covers rows*cols of the largest job, y = 2 * njobs (job, CD part).
+// Positions a transform of job jb runs over: rows x cols, or rows x dst_ld
+// when a forward transform fills the padding columns.
+template <bool INV, typename T>
+__host__ __device__ inline long fft_positions(const FftJob<T>& jb) {
+    return (long)jb.rows * (!INV && jb.fill && !jb.half ? jb.dst_ld : jb.cols);
+}
+
+// grid: x covers the positions of the largest job, y = 2 * njobs (job, CD part).
 template <int P, bool INV, typename T>
 __global__ void __launch_bounds__(256)
 tube_fft_kernel(FftJobs2<T> jobs, const typename Vec2<T>::type* __restrict__ tw) {
@@ -294,7 +301,14 @@ tube_fft_kernel(FftJobs2<T> jobs, const typename Vec2<T>::type* __restrict__ tw)
     const int part = by & 1;                         // 0: X1 (planes 0,1), 1: X2 (planes 2,3)
     const FftJob<T> jb = jobs.j[job];
     const long e = (long)bx * blockDim.x + threadIdx.x;
-    if (e >= (long)jb.rows * jb.cols || part >= jb.parts) return;
+    if (e >= fft_positions<INV>(jb) || part >= jb.parts) return;
+    if constexpr (!INV) {
+        if (jb.fill && !jb.half) {
+            const int i = (int)(e / jb.dst_ld);
+            tube_fft_rc<P, false, T, 0, true>(jb, part, i, (int)(e - (long)i * jb.dst_ld), tw);
+            return;
+        }
+    }
     tube_fft_one<P, INV, T>(jb, part, e, tw);
 }
 
@@ -304,7 +318,7 @@ hipError_t launch_p(const FftJob<T>* jobs, int njobs, const Twiddles& tw, hipStr
     long maxc = 0;
     for (int q = 0; q < njobs; ++q) {
         pk.j[q] = jobs[q];
-        maxc = (long)jobs[q].rows * jobs[q].cols > maxc ? (long)jobs[q].rows * jobs[q].cols : maxc;
+        maxc = fft_positions<INV>(jobs[q]) > maxc ? fft_positions<INV>(jobs[q]) : maxc;
     }
     const dim3 block(256);
     const dim3 grid((unsigned)((maxc + 255) / 256), 2 * njobs);

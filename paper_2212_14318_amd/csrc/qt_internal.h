@@ -33,6 +33,10 @@ struct FftJob {
     // reads those p/2 + 1 faces (the rest are conj(X^[p - f])) and writes
     // the real plane of p faces.
     int half = 0;
+    // fill = 1 (forward, dst_ld > cols, a library workspace as destination):
+    // the register-resident kernels also write the padding columns of the
+    // destination rows, as zero tubes, so that no line is written in part
+    int fill = 0;
 };
 
 // Bluestein tables of one p (lengths without a register-resident kernel):

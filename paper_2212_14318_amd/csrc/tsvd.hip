@@ -997,7 +997,7 @@ int run_tsvd(int m, int n, int p, const T* A, T* U, T* S, T* V, T* sigma_out, in
     T* sig = sigma_out ? sigma_out : reinterpret_cast<T*>(ws + L.sig);
     const int lda = (int)fourier_ld(n), ldu = (int)fourier_ld(m), ldv = (int)fourier_ld(n);
 
-    FftJob<T> fwd[1] = {{A, Ah, m, n, n, lda, 0}};
+    FftJob<T> fwd[1] = {{A, Ah, m, n, n, lda, 0, 2, 0, 1}};
     if (launch_tube_fft<T>(p, false, fwd, 1, tw, stream) != hipSuccess) return QT_ERR_HIP;
     if (launch_tsvd_pairs<T>(m, n, p, Ah, lda, Uh, ldu, Vh, ldv, sig, ws + L.pairs, stream) != hipSuccess)
         return QT_ERR_HIP;
