@@ -750,7 +750,12 @@ tsvd_round_kernel(TsvdArgs<T> a, int bs, int t, int sweep) {
     using V = typename Cx<T>::type;
     __shared__ __attribute__((aligned(16))) char s_cols[LDS];
     __shared__ int s_rot;
-    const PairView<T> pv = pair_view(a, blockIdx.y);
+    // the self-paired frequencies (f = 0, and p / 2 for even p) first: their
+    // quaternion steps and updates take longest, and dispatched last they
+    // would set the end of every round
+    const int y = blockIdx.y;
+    const int f = (a.p % 2 == 0 && a.p > 1) ? (y == 0 ? 0 : y == 1 ? a.p / 2 : y - 1) : y;
+    const PairView<T> pv = pair_view(a, f);
     if (pv.hdr->done) return;
     const int nu = pv.nu, nb = (nu + bs - 1) / bs, nbp = nb + (nb & 1);
     const int q = blockIdx.x;
