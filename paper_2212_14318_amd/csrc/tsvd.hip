@@ -166,6 +166,7 @@ __device__ __forceinline__ V partner_at(const V* x, int k, int h) {
 template <typename T, typename V>
 __device__ __forceinline__ bool jacobi_pair(V* xi, V* xj, V* qi, V* qj, int h, int hq, bool quat, T tol, Acc negl2, int lane) {
     Acc al = 0, be = 0, g1r = 0, g1i = 0, g2r = 0, g2i = 0;
+#pragma unroll 4
     for (int k = lane; k < h; k += 64) {
         const V a0 = xi[k], a1 = xi[k + h], b0 = xj[k], b1 = xj[k + h];
         const Acc a0x = a0.x, a0y = a0.y, a1x = a1.x, a1y = a1.y;
@@ -199,6 +200,7 @@ __device__ __forceinline__ bool jacobi_pair(V* xi, V* xj, V* qi, V* qj, int h, i
     T cs, sn;
     rotation<T, V>(al, be, g1r, g1i, g2r, g2i, gn, e1c, e2c, cs, sn);
     auto apply = [&](V* ci, V* cj, int hh) {
+#pragma unroll 4
         for (int k = lane; k < hh; k += 64) {
             const V a0 = ci[k], a1 = ci[k + hh], b0 = cj[k], b1 = cj[k + hh];
             V c0 = cmul(e1c, b0), c1 = cmul(e1c, b1);
