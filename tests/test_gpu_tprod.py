@@ -47,11 +47,14 @@ def test_tube_fft_unaligned_faces(rows, cols, p):
     """Faces whose size is not a multiple of 32 reals (each face starts at a
     different offset within a cache line), multi-block: forward from the
     dense layout into padded Fourier rows (FP32 and split words), inverse from
-    the padded rows back to the dense layout.  64 x 64 is the aligned control."""
+    the padded rows back to the dense layout.  64 x 64 is the aligned control.
+    The caller's padding columns keep their contents (only the library's own
+    workspaces get their padding written)."""
     X = synth.quat_tensor(rows, cols, p, seed=170 + p)
     dev = device()
-    F = torch.empty((4, p, rows, nat.qt_fourier_ld(cols)), device=dev)
+    F = torch.full((4, p, rows, nat.qt_fourier_ld(cols)), 7.0, device=dev)
     tube_fft(to_dev(X), out=F)
+    assert bool((F[..., cols:] == 7.0).all())
     w1 = np.fft.fft(X[0] + 1j * X[1], axis=0)
     w2 = np.fft.fft(X[2] + 1j * X[3], axis=0)
     want = np.stack([w1.real, w1.imag, w2.real, w2.imag])
@@ -59,8 +62,9 @@ def test_tube_fft_unaligned_faces(rows, cols, p):
     back = torch.empty((4, p, rows, cols), device=dev)
     tube_fft(F, inverse=True, cols=cols, out=back)
     assert rel_err(to_np(back), X) < 2e-6
-    W = torch.empty_like(F)
+    W = torch.full_like(F, 7.0)
     tube_fft(to_dev(X), precision="split_bf16", out=W)
+    assert bool((W[..., cols:] == 7.0).all())
     hi, lo = _unpack_split_words(W[..., :cols])
     assert rel_err(hi + lo, want) < 2e-5
 

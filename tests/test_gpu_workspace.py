@@ -117,3 +117,52 @@ def test_injected_allocation_failure_launches_nothing():
     assert out.returncode == 0, out.stderr[-2000:]
     st, untouched = out.stdout.split()[-2:]
     assert int(st) == nat.QT_ERR_ALLOC and untouched == "True"
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
+def test_tprod_workspace_contents_do_not_leak(prec):
+    """A caller workspace full of NaN bit patterns gives the same result, bit
+    for bit, as a zeroed one: with padded Fourier rows (45 and 33 columns,
+    padded to 48 and 36) nothing the products or transforms read comes from
+    the workspace's previous contents."""
+    m, n, s, p = 37, 45, 33, 10
+    A, B = synth.quat_tensor(m, n, p, seed=4450), synth.quat_tensor(n, s, p, seed=4451)
+    Ad, Bd = to_dev(A), to_dev(B)
+    need = nat.qt_workspace_size(m, n, s, p, nat.PRECISIONS[prec])
+    ws_nan = torch.full((need,), 255, dtype=torch.uint8, device=device())
+    ws_zero = torch.zeros((need,), dtype=torch.uint8, device=device())
+    C1 = ops.tprod(Ad, Bd, precision=prec, ws=ws_nan)
+    C2 = ops.tprod(Ad, Bd, precision=prec, ws=ws_zero)
+    torch.cuda.synchronize()
+    assert torch.isfinite(C1).all()
+    assert torch.equal(C1, C2)
+    assert rel_err(to_np(C1), oracle.tprod(A, B)) < 5e-5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
+def test_batched_workspace_contents_do_not_leak(prec):
+    """The batched path on a workspace full of NaN bit patterns: the same
+    results, bit for bit, as on a zeroed one (padded Fourier rows in every
+    problem, a p without a batched transform among them)."""
+    sizes = [(40, 17, 33, 8), (16, 63, 21, 12), (70, 30, 9, 61)]
+    As, Bs, refs = [], [], []
+    for i, (m, n, s, p) in enumerate(sizes):
+        A, B = synth.quat_tensor(m, n, p, seed=4460 + i), synth.quat_tensor(n, s, p, seed=4470 + i)
+        As.append(to_dev(A)); Bs.append(to_dev(B))
+        refs.append(oracle.tprod(A, B))
+    outs = []
+    for fill in (255, 0):
+        Cs = [torch.empty((4, p, m, s), device=device()) for (m, n, s, p) in sizes]
+        probs = (nat.qt_problem * len(sizes))()
+        for k, ((m, n, s, p), A, B, C) in enumerate(zip(sizes, As, Bs, Cs)):
+            probs[k] = nat.qt_problem(m, n, s, p, A.data_ptr(), B.data_ptr(), C.data_ptr())
+        need = nat.qt_batched_workspace_size(len(sizes), probs, nat.PRECISIONS[prec])
+        ws = torch.full((need,), fill, dtype=torch.uint8, device=device())
+        assert nat.qt_tprod_batched(len(sizes), probs, nat.PRECISIONS[prec], ws.data_ptr(), need,
+                                    _stream()) == nat.QT_OK
+        torch.cuda.synchronize()
+        outs.append(Cs)
+    for C1, C2, ref in zip(outs[0], outs[1], refs):
+        assert torch.isfinite(C1).all()
+        assert torch.equal(C1, C2)
+        assert rel_err(to_np(C1), ref) < 5e-5
