@@ -333,6 +333,27 @@ __device__ void write_slot(T* Yh, int ld, int p, int half, int f, int g, int slo
     }
 }
 
+// Entry i (0 <= i < 2 half) of the column vector of slot `slot`, placed as
+// write_slot places it.
+template <typename T, typename V>
+__device__ __forceinline__ void place_entry(T* Yh, int ld, int p, int half, int f, int g, int slot, int i, V v) {
+    const size_t plane = (size_t)p * half * ld;
+    const bool second = slot >= half;
+    const int j = second ? slot - half : slot;
+    if (i < half) {
+        const int pf = second ? 2 : 0;
+        const size_t rf = ((size_t)f * half + i) * ld + j;
+        Yh[pf * plane + rf] = v.x;
+        Yh[(pf + 1) * plane + rf] = v.y;
+    } else {
+        const V bg = second ? cconj(v) : cneg(cconj(v));
+        const int pg = second ? 0 : 2;
+        const size_t rg = ((size_t)g * half + (i - half)) * ld + j;
+        Yh[pg * plane + rg] = bg.x;
+        Yh[(pg + 1) * plane + rg] = bg.y;
+    }
+}
+
 // Geometry of frequency pair f: which matrix is orthogonalised and where its
 // scratch lives.
 template <typename T>
@@ -488,7 +509,8 @@ struct FinishSmem {
 // normalised left vectors (completed to an orthonormal basis), and both
 // vector sets placed at f and -f.  Whole workgroup.
 template <typename T>
-__device__ void pair_finish(const TsvdArgs<T>& a, const PairView<T>& pv, T scale, Acc negl2, FinishSmem<T>& sm) {
+__device__ void pair_finish(const TsvdArgs<T>& a, const PairView<T>& pv, T scale, Acc negl2, FinishSmem<T>& sm,
+                            bool place = true) {
     using V = typename Cx<T>::type;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int p = a.p, f = pv.f, g = pv.g, r = pv.r, c = pv.c, nu = pv.nu, nL = pv.nL, R = pv.R, Rq = pv.Rq;
@@ -602,6 +624,13 @@ __device__ void pair_finish(const TsvdArgs<T>& a, const PairView<T>& pv, T scale
     }
     __syncthreads();
 
+    if (!place) {
+        // the placement runs as a kernel of its own: it needs the rank order
+        // of the rotation columns, kept where the completion's coefficients were
+        int* gperm = reinterpret_cast<int*>(coef);
+        for (int rho = tid; rho < nu; rho += kThreads) gperm[rho] = s_perm[rho];
+        return;
+    }
     // place the vectors: rank rho goes to slot rho (quaternion columns) or
     // to slot rho / 2 (+ half for odd rho) -- the interleaving of f and -f
     T* Lh = tall ? a.Uh : a.Vh;
@@ -880,7 +909,44 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads) tsvd_finish_kernel(TsvdArgs<T> a) {
     __shared__ FinishSmem<T> sm;
     const PairView<T> pv = pair_view(a, blockIdx.x);
-    pair_finish(a, pv, (T)pv.hdr->scale, pv.hdr->negl2, sm);
+    pair_finish(a, pv, (T)pv.hdr->scale, pv.hdr->negl2, sm, false);
+}
+
+// Placement of the block path's vectors, spread over many workgroups: grid
+// (tiles of 32 ranks, frequency pairs, 2), z = 0 the left vectors L, z = 1
+// the rotation columns Q in rank order.  A tile of 32 columns x 64 entries is
+// read along the columns into LDS and written along the slots, so that
+// consecutive lanes store consecutive columns of a row.
+template <typename T>
+__global__ void __launch_bounds__(256) tsvd_place_kernel(TsvdArgs<T> a) {
+    using V = typename Cx<T>::type;
+    constexpr int TC = 32, TI = 64;
+    __shared__ V tile[TC][TI + 1];
+    const PairView<T> pv = pair_view(a, blockIdx.y);
+    const bool left = blockIdx.z == 0;
+    const int count = left ? pv.nL : pv.nu;
+    const int rho0 = blockIdx.x * TC;
+    if (rho0 >= count) return;
+    const int half = left ? pv.r : pv.c, R = 2 * half, tid = threadIdx.x;
+    const V* src = left ? pv.L : pv.Q;
+    const int* perm = reinterpret_cast<const int*>(pv.coef);
+    T* Yh = left == pv.tall ? a.Uh : a.Vh;
+    const int ld = left == pv.tall ? a.ldu : a.ldv;
+    for (int i0 = 0; i0 < R; i0 += TI) {
+        for (int e = tid; e < TC * TI; e += 256) {
+            const int cl = e / TI, il = e % TI, rho = rho0 + cl, i = i0 + il;
+            if (rho < count && i < R) tile[cl][il] = src[(size_t)(left ? rho : perm[rho]) * R + i];
+        }
+        __syncthreads();
+        for (int e = tid; e < TC * TI; e += 256) {
+            const int cl = e % TC, il = e / TC, rho = rho0 + cl, i = i0 + il;
+            if (rho < count && i < R) {
+                const int slot = pv.quat ? rho : rho / 2 + ((rho & 1) ? half : 0);
+                place_entry<T, V>(Yh, ld, a.p, half, pv.f, pv.g, slot, i, tile[cl][il]);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // S^ from sigma: S^1[f](i, i) = sigma[f][i], every other entry zero.
@@ -987,6 +1053,7 @@ hipError_t launch_tsvd_pairs(int m, int n, int p, const T* Ah, int lda, T* Uh, i
                            sweep);
     }
     hipLaunchKernelGGL(tsvd_finish_kernel<T>, dim3(npairs), dim3(kThreads), 0, stream, args);
+    hipLaunchKernelGGL(tsvd_place_kernel<T>, dim3((2 * r + 31) / 32, npairs, 2), dim3(256), 0, stream, args);
     return hipGetLastError();
 }
 
