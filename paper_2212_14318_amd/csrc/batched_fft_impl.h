@@ -17,12 +17,13 @@ __global__ void __launch_bounds__(256)
 batched_fft_kernel(const BatchFftJob* __restrict__ jobs, const BatchFftItem* __restrict__ items) {
     const BatchFftItem item = items[xcd_contiguous(blockIdx.x, gridDim.x)];
     const BatchFftJob bj = jobs[item.job];
-    const int w = bj.fill ? bj.dst_ld : bj.cols;    // positions per row
+    const bool fill = !INV && bj.fill;              // (inverse jobs never fill)
+    const int w = fill ? bj.dst_ld : bj.cols;       // positions per row
     const long e = (long)item.e0 + threadIdx.x;
     if (e >= (long)bj.rows * w) return;
     const FftJob<float> jb{bj.src, bj.dst, bj.rows, bj.cols, bj.src_ld, bj.dst_ld, bj.pack};
     if constexpr (!INV) {
-        if (bj.fill) {
+        if (fill) {
             const int i = (int)(e / w);
             tube_fft_rc<P, false, float, POL, true>(jb, item.part, i, (int)(e - (long)i * w), bj.tw);
             return;
