@@ -777,7 +777,7 @@ __device__ __forceinline__ void apply_coefficients(V* QI, V* QJ, int nI, int nk,
 // max(m, n) <= 64, 4 for <= 256), 0 for the looping step of longer columns.
 template <typename T, size_t LDS, int KR>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LDS == kBlockLdsHalf ? 4 : 2)))
-tsvd_round_kernel(TsvdArgs<T> a, int bs, int t, int sweep) {
+tsvd_round_kernel(TsvdArgs<T> a, int bs_c, int t, int sweep) {
     using V = typename Cx<T>::type;
     __shared__ __attribute__((aligned(16))) char s_cols[LDS];
     __shared__ int s_rot;
@@ -788,6 +788,12 @@ tsvd_round_kernel(TsvdArgs<T> a, int bs, int t, int sweep) {
     const int f = (a.p % 2 == 0 && a.p > 1) ? (y == 0 ? 0 : y == 1 ? a.p / 2 : y - 1) : y;
     const PairView<T> pv = pair_view(a, f);
     if (pv.hdr->done) return;
+    // a quaternion pair has half as many units, each step and update costs
+    // about twice as much: blocks of half the size give it the same number
+    // of block pairs and rounds per sweep as the complex pairs, and
+    // workgroups that finish with theirs (ceil(bs / 2) units never needs
+    // more rounds than bs units of the complex pairs)
+    const int bs = pv.quat ? (bs_c + 1) / 2 : bs_c;
     const int nu = pv.nu, nb = (nu + bs - 1) / bs, nbp = nb + (nb & 1);
     const int q = blockIdx.x;
     if (t >= nbp - 1 || q >= nbp / 2) return;      // a shorter schedule (quaternion pair)
