@@ -667,9 +667,9 @@ __global__ void __launch_bounds__(kThreads) tsvd_pair_kernel(TsvdArgs<T> a) {
 // block), and writes the columns back.  Every unit pair is visited once per
 // sweep, as in the single-workgroup order, with one global read and write of
 // a column per block pair instead of one per unit pair.
-// The rotations are not applied to the staged rotation columns one by one:
-// the workgroup accumulates their product W over its nk units in LDS and
-// applies it once at the end, Q_j <- sum_i Q_i A_ij + partner(Q_i) B_ij.
+// The rotation columns are not staged: the workgroup accumulates the product
+// W of its rotations over its nk units in LDS and applies it once at the end,
+// Q_j <- sum_i Q_i A_ij + partner(Q_i) B_ij.
 // A Jacobi step maps unit columns to combinations of this form, and since
 // partner is conjugate-linear with partner(partner(x)) = -x, the coefficient
 // column (A_j; B_j) of unit j transforms under a step exactly as a
