@@ -134,14 +134,15 @@ __device__ __forceinline__ double wave_total(double v) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
-// Parameters of a Jacobi step from the wave-summed inner products (gn =
-// |gamma| > 0): the phase e = gamma / |gamma| (applied as x_j conj(e)) and
+// Parameters of a Jacobi step from the wave-summed inner products (gn2 =
+// |gamma|^2 > 0): the phase e = gamma / |gamma| (applied as x_j conj(e)) and
 // the plane rotation (cs, sn) that then zeroes the real inner product, formed
-// in double and rounded once to T (one division).
+// in double (two reciprocal square roots, at most one division) and rounded
+// once to T.
 template <typename T, typename V>
-__device__ __forceinline__ void rotation(Acc al, Acc be, Acc g1r, Acc g1i, Acc g2r, Acc g2i, Acc gn, V& e1c,
+__device__ __forceinline__ void rotation(Acc al, Acc be, Acc g1r, Acc g1i, Acc g2r, Acc g2i, Acc gn2, V& e1c,
                                          V& e2c, T& cs, T& sn) {
-    const Acc ign = Acc(1) / gn;
+    const Acc ign = rsqrt(gn2);
     e1c = V{T(g1r * ign), T(-g1i * ign)};
     e2c = V{T(g2r * ign), T(-g2i * ign)};
     const Acc zeta = (be - al) * (Acc(0.5) * ign);
@@ -149,7 +150,7 @@ __device__ __forceinline__ void rotation(Acc al, Acc be, Acc g1r, Acc g1i, Acc g
     // |t| = 1 / (|zeta| + sqrt(1 + zeta^2)) = (sqrt(1 + zeta^2) - |zeta|)
     const Acc w = sqrt(Acc(1) + az * az);
     const Acc at = az > Acc(1) ? Acc(1) / (az + w) : w - az;
-    const Acc csd = Acc(1) / sqrt(Acc(1) + at * at);
+    const Acc csd = rsqrt(Acc(1) + at * at);
     cs = T(csd);
     sn = T(csd * (zeta >= 0 ? at : -at));
 }
@@ -192,13 +193,15 @@ __device__ __forceinline__ bool jacobi_pair(V* xi, V* xj, V* qi, V* qj, int h, i
     // a column at rounding level of the whole matrix belongs to the null
     // space: rotating it only stirs rounding errors (and never converges)
     if (al <= negl2 || be <= negl2) return false;
-    const Acc gn = sqrt(g1r * g1r + g1i * g1i + g2r * g2r + g2i * g2i);
-    if (!(gn > (Acc)tol * sqrt(al * be))) return false;
+    // |gamma| > tol sqrt(al be), compared in squares (no square roots on the
+    // path of a pair that does not rotate)
+    const Acc gn2 = g1r * g1r + g1i * g1i + g2r * g2r + g2i * g2i;
+    if (!(gn2 > (Acc)tol * (Acc)tol * (al * be))) return false;
     // x_j <- x_j conj(e), e = gamma / |gamma| (a unit quaternion, or a complex
     // phase when g2 = 0): afterwards x_i^* x_j = |gamma| is real
     V e1c, e2c;
     T cs, sn;
-    rotation<T, V>(al, be, g1r, g1i, g2r, g2i, gn, e1c, e2c, cs, sn);
+    rotation<T, V>(al, be, g1r, g1i, g2r, g2i, gn2, e1c, e2c, cs, sn);
     auto apply = [&](V* ci, V* cj, int hh) {
 #pragma unroll 4
         for (int k = lane; k < hh; k += 64) {
@@ -268,11 +271,13 @@ __device__ __forceinline__ bool jacobi_pair_reg(V* xi, V* xj, V* qi, V* qj, int 
         g2i = wave_total(g2i);
     }
     if (al <= negl2 || be <= negl2) return false;
-    const Acc gn = sqrt(g1r * g1r + g1i * g1i + g2r * g2r + g2i * g2i);
-    if (!(gn > (Acc)tol * sqrt(al * be))) return false;
+    // |gamma| > tol sqrt(al be), compared in squares (no square roots on the
+    // path of a pair that does not rotate)
+    const Acc gn2 = g1r * g1r + g1i * g1i + g2r * g2r + g2i * g2i;
+    if (!(gn2 > (Acc)tol * (Acc)tol * (al * be))) return false;
     V e1c, e2c;
     T cs, sn;
-    rotation<T, V>(al, be, g1r, g1i, g2r, g2i, gn, e1c, e2c, cs, sn);
+    rotation<T, V>(al, be, g1r, g1i, g2r, g2i, gn2, e1c, e2c, cs, sn);
     auto rot = [&](V& u0, V& u1, V& w0, V& w1) {
         V r0 = cmul(e1c, w0), r1 = cmul(e1c, w1);
         if (quat) {
