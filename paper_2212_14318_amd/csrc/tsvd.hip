@@ -137,8 +137,8 @@ __device__ __forceinline__ double wave_total(double v) {
 // Parameters of a Jacobi step from the wave-summed inner products (gn2 =
 // |gamma|^2 > 0): the phase e = gamma / |gamma| (applied as x_j conj(e)) and
 // the plane rotation (cs, sn) that then zeroes the real inner product, formed
-// in double (two reciprocal square roots, at most one division) and rounded
-// once to T.
+// in double (reciprocal square roots and a refined reciprocal, no division)
+// and rounded once to T.
 template <typename T, typename V>
 __device__ __forceinline__ void rotation(Acc al, Acc be, Acc g1r, Acc g1i, Acc g2r, Acc g2i, Acc gn2, V& e1c,
                                          V& e2c, T& cs, T& sn) {
@@ -147,9 +147,22 @@ __device__ __forceinline__ void rotation(Acc al, Acc be, Acc g1r, Acc g1i, Acc g
     e2c = V{T(g2r * ign), T(-g2i * ign)};
     const Acc zeta = (be - al) * (Acc(0.5) * ign);
     const Acc az = fabs(zeta);
-    // |t| = 1 / (|zeta| + sqrt(1 + zeta^2)) = (sqrt(1 + zeta^2) - |zeta|)
-    const Acc w = sqrt(Acc(1) + az * az);
-    const Acc at = az > Acc(1) ? Acc(1) / (az + w) : w - az;
+    // |t| = 1 / (|zeta| + sqrt(1 + zeta^2)) = (sqrt(1 + zeta^2) - |zeta|);
+    // sqrt(y) = y rsqrt(y), and for |zeta| > 1 the reciprocal of d = |zeta| +
+    // w >= 2 is the hardware estimate refined by two Newton steps (each one
+    // doubles the correct bits), without the scaling of a general division
+    const Acc y = Acc(1) + az * az;
+    const Acc w = y * rsqrt(y);
+    Acc at;
+    if (az > Acc(1)) {
+        const Acc d = az + w;
+        Acc r = __builtin_amdgcn_rcp(d);
+        r = fma(r, fma(-d, r, Acc(1)), r);
+        r = fma(r, fma(-d, r, Acc(1)), r);
+        at = r;
+    } else {
+        at = w - az;
+    }
     const Acc csd = rsqrt(Acc(1) + at * at);
     cs = T(csd);
     sn = T(csd * (zeta >= 0 ? at : -at));
